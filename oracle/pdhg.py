@@ -273,6 +273,7 @@ def solve(A, c, lc, uc, lv, uv, params: Params | None = None, x0=None, y0=None):
     else:
         nrm, _ = power_norm(At, p.power_max_iter, p.power_tol)
         eta = 0.998 / nrm if nrm > 0 else 1.0
+    t_iter = time.perf_counter()
 
     x = np.zeros(n) if x0 is None else np.asarray(x0, dtype=np.float64) / dc
     y = np.zeros(m) if y0 is None else np.asarray(y0, dtype=np.float64) / dr
@@ -331,6 +332,8 @@ def solve(A, c, lc, uc, lv, uv, params: Params | None = None, x0=None, y0=None):
             status = TIME_LIMIT
         if status is not None:
             info = {key: kk[key] for key in ("pobj", "dobj", "rel_gap", "rel_primal", "rel_dual", "rel_kkt")}
+            info["setup_s"] = t_iter - t_start
+            info["iter_s"] = time.perf_counter() - t_iter
             return Result(xu, yu, kk["r"], status, t, restarts, info, omega, eta, dr, dc, trace, log)
 
         if restart_decision(r, r0, r_prev, k, t, p):

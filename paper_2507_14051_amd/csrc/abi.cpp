@@ -1,0 +1,384 @@
+// C ABI entry points: argument checks, workspace layout, setup (validation,
+// CSR copy, transpose, rescaling, power iteration) and error reporting.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "hlp_internal.h"
+
+namespace hlp {
+
+namespace {
+thread_local std::string g_err;
+constexpr size_t kAlign = 256;
+
+inline size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(int64_t count) {
+    size_t bytes = up(sizeof(T) * (size_t)std::max<int64_t>(count, 1));
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+const char* flag_message(int f) {
+  if (f & 1) return "row_ptr must start at 0 and end at nnz";
+  if (f & 2) return "row_ptr must be nondecreasing";
+  if (f & 4) return "column index out of range";
+  if (f & 8) return "column indices must be strictly increasing within each row";
+  if (f & 16) return "matrix values must be finite";
+  if (f & 32) return "c must be finite";
+  if (f & 64) return "a bound is NaN";
+  if (f & 128) return "a lower bound exceeds its upper bound";
+  if (f & 256) return "a lower bound is +inf or an upper bound is -inf";
+  return "invalid input";
+}
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+}  // namespace
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+hlp_err hip_fail(hipError_t e, const char* what) {
+  g_err = std::string("HIP error ") + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ") in " + what;
+  return HLP_EHIP;
+}
+
+int lanes_for(double mean) {
+  int L = 1;
+  while (L < 64 && L < mean) L <<= 1;
+  return L;
+}
+
+size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t precision) {
+  Carver c{static_cast<char*>(base)};
+  const bool mixed = precision == HLP_MIXED;
+  const int64_t N = std::max<int64_t>(m, n);
+  hlp_lp tmp;
+  hlp_lp* L = lp ? lp : &tmp;
+  L->rp = c.take<int32_t>((int64_t)m + 1);
+  L->col = c.take<int32_t>(nnz);
+  L->val0 = c.take<double>(nnz);
+  L->val = c.take<double>(nnz);
+  L->cp = c.take<int32_t>((int64_t)n + 1);
+  L->row = c.take<int32_t>(nnz);
+  L->tval0 = c.take<double>(nnz);
+  L->tval = c.take<double>(nnz);
+  L->val32 = mixed ? c.take<float>(nnz) : nullptr;
+  L->tval32 = mixed ? c.take<float>(nnz) : nullptr;
+  L->dr = c.take<double>(m);
+  L->dc = c.take<double>(n);
+  L->ct = c.take<double>(n);
+  L->lvt = c.take<double>(n);
+  L->uvt = c.take<double>(n);
+  L->lct = c.take<double>(m);
+  L->uct = c.take<double>(m);
+  L->x = c.take<double>(n);
+  L->xa = c.take<double>(n);
+  L->xbar = c.take<double>(n);
+  L->xh = c.take<double>(n);
+  L->dxv = c.take<double>(n);
+  L->rbuf = c.take<double>(n);
+  L->y = c.take<double>(m);
+  L->ya = c.take<double>(m);
+  L->yh = c.take<double>(m);
+  if (mixed) {
+    L->x32 = c.take<float>(n);
+    L->xa32 = c.take<float>(n);
+    L->xbar32 = c.take<float>(n);
+    L->xh32 = c.take<float>(n);
+    L->dx32 = c.take<float>(n);
+    L->c32 = c.take<float>(n);
+    L->lv32 = c.take<float>(n);
+    L->uv32 = c.take<float>(n);
+    L->y32 = c.take<float>(m);
+    L->ya32 = c.take<float>(m);
+    L->yh32 = c.take<float>(m);
+    L->lc32 = c.take<float>(m);
+    L->uc32 = c.take<float>(m);
+    L->b32 = c.take<float>(m);
+  }
+  // FP64 centre and residual vectors (mixed); the adjoint also uses them.
+  L->xcen = c.take<double>(n);
+  L->ycen = c.take<double>(m);
+  L->axc = c.take<double>(m);
+  L->atyc = c.take<double>(n);
+  // reductions: 4 regions of partial_blocks x 8 doubles (lanes per row <= 64)
+  L->partial_blocks = (N * 64 + 255) / 256 + 1;
+  L->partials = c.take<double>(4 * L->partial_blocks * 8);
+  L->results = c.take<double>(NSLOT * NQ);
+  L->pstate = c.take<PowerState>(1);
+  L->flags = c.take<int32_t>(4);
+  // transpose scratch
+  L->kA = c.take<int32_t>(nnz);
+  L->kB = c.take<int32_t>(std::max<int64_t>(nnz, (int64_t)n + 1));
+  L->vA = c.take<int32_t>(nnz);
+  L->vB = c.take<int32_t>(nnz);
+  L->rowof = c.take<int32_t>(nnz);
+  const int64_t nbr = (nnz + 4095) / 4096;
+  L->hist_len = 256 * std::max<int64_t>(nbr, 1);
+  L->hist = c.take<int32_t>(L->hist_len);
+  L->scan_tmp_len = std::max<int64_t>(L->hist_len, (int64_t)n + 1) / 1024 + 2;
+  L->scan_tmp = c.take<int32_t>(L->scan_tmp_len);
+  // power iteration vectors alias iteration buffers (setup only)
+  L->pv = L->rbuf;
+  L->pw = L->atyc;
+  L->pu = L->axc;
+  return c.off;
+}
+
+}  // namespace hlp
+
+using namespace hlp;
+
+extern "C" {
+
+const char* hlp_last_error(void) { return g_err.c_str(); }
+
+hlp_err hlp_params_default(hlp_params* p) {
+  if (!p) {
+    set_error("hlp_params_default: NULL");
+    return HLP_EINVAL;
+  }
+  std::memset(p, 0, sizeof(*p));
+  p->tol = 1e-8;
+  p->max_iter = 10000000;
+  p->time_limit_s = 3600.0;
+  p->eval_freq = 64;
+  p->precision = HLP_FP64;
+  p->gamma = 1.0;
+  p->beta_sufficient = 0.2;
+  p->beta_necessary = 0.8;
+  p->beta_artificial = 0.36;
+  p->kp = 0.99;
+  p->ki = 0.01;
+  p->kd = 0.0;
+  p->omega0 = 1.0;
+  p->eta_override = 0.0;
+  p->ruiz_iters = 10;
+  p->pock_chambolle = 1;
+  p->power_max_iter = 5000;
+  p->restart_to_current = 0;
+  p->power_tol = 1e-8;
+  p->pid_min_norm = 1e-10;
+  p->trace_iters = 0;
+  p->debug_poison_iter = 0;
+  return HLP_OK;
+}
+
+static hlp_err check_sizes(int32_t m, int32_t n, int64_t nnz) {
+  if (m < 0 || n < 0 || nnz < 0) {
+    set_error("m, n and nnz must be nonnegative");
+    return HLP_EINVAL;
+  }
+  if (nnz >= (int64_t(1) << 31) || m >= INT32_MAX - 1 || n >= INT32_MAX - 1) {
+    set_error("nnz >= 2^31 or a dimension near 2^31 is not supported (int32 device indexing)");
+    return HLP_EUNSUPPORTED;
+  }
+  return HLP_OK;
+}
+
+hlp_err hlp_workspace_bytes(int32_t m, int32_t n, int64_t nnz, const hlp_params* p, size_t* bytes) {
+  if (!bytes) {
+    set_error("hlp_workspace_bytes: NULL output");
+    return HLP_EINVAL;
+  }
+  HLP_TRY(check_sizes(m, n, nnz));
+  hlp_params d;
+  hlp_params_default(&d);
+  if (!p) p = &d;
+  *bytes = carve(nullptr, nullptr, m, n, nnz, p->precision);
+  return HLP_OK;
+}
+
+static hlp_err read_flags(hlp_lp* lp, int* out) {
+  HLP_HIP(hipMemcpyAsync(out, lp->flags, sizeof(int), hipMemcpyDeviceToHost, lp->stream));
+  HLP_HIP(hipStreamSynchronize(lp->stream));
+  return HLP_OK;
+}
+
+static hlp_err validate_and_scale_vectors(hlp_lp* lp, const double* c, const double* lc,
+                                          const double* uc, const double* lv, const double* uv) {
+  if ((lp->n && (!c || !lv || !uv)) || (lp->m && (!lc || !uc))) {
+    set_error("NULL objective or bound vector");
+    return HLP_EINVAL;
+  }
+  HLP_HIP(launch_fill(reinterpret_cast<double*>(lp->flags), 0.0, 1, lp->stream));
+  HLP_HIP(launch_validate_vectors(c, lc, uc, lv, uv, lp->m, lp->n, lp->flags, lp->stream));
+  int f = 0;
+  HLP_TRY(read_flags(lp, &f));
+  if (f) {
+    set_error(flag_message(f));
+    return HLP_EINVAL;
+  }
+  HLP_HIP(launch_scale_vectors(lp, c, lc, uc, lv, uv));
+  double q[2] = {0.0, 0.0};
+  HLP_HIP(hipMemcpyAsync(q, lp->results + SLOT_TMP * NQ, sizeof(q), hipMemcpyDeviceToHost, lp->stream));
+  HLP_HIP(hipStreamSynchronize(lp->stream));
+  lp->norm_c = std::sqrt(q[0]);
+  lp->norm_b = std::sqrt(q[1]);
+  return HLP_OK;
+}
+
+hlp_err hlp_lp_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                      const double* val, const double* c, const double* lc, const double* uc,
+                      const double* lv, const double* uv, const hlp_params* p, void* workspace,
+                      size_t workspace_bytes, void* hip_stream, hlp_lp** out) {
+  if (!out) {
+    set_error("hlp_lp_create: NULL out");
+    return HLP_EINVAL;
+  }
+  *out = nullptr;
+  HLP_TRY(check_sizes(m, n, nnz));
+  if (!row_ptr || (nnz > 0 && (!col_idx || !val)) || !workspace) {
+    set_error("hlp_lp_create: NULL input pointer");
+    return HLP_EINVAL;
+  }
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) {
+    set_error("workspace must be 256-byte aligned");
+    return HLP_EINVAL;
+  }
+  hlp_params d;
+  hlp_params_default(&d);
+  if (!p) p = &d;
+  if (p->precision != HLP_FP64 && p->precision != HLP_MIXED) {
+    set_error("unknown precision");
+    return HLP_EINVAL;
+  }
+  if (p->ruiz_iters < 0 || p->power_max_iter < 1 || !(p->power_tol >= 0.0) ||
+      !(p->eta_override >= 0.0) || !std::isfinite(p->eta_override)) {
+    set_error("bad setup parameters (ruiz_iters >= 0, power_max_iter >= 1, power_tol >= 0, finite eta_override >= 0)");
+    return HLP_EINVAL;
+  }
+  size_t need = carve(nullptr, nullptr, m, n, nnz, p->precision);
+  if (workspace_bytes < need) {
+    set_error("workspace too small: need " + std::to_string(need) + " bytes");
+    return HLP_ENOMEM;
+  }
+  hlp_lp* lp = new (std::nothrow) hlp_lp();
+  if (!lp) {
+    set_error("out of host memory");
+    return HLP_ENOMEM;
+  }
+  const double t0 = now_s();
+  lp->m = m;
+  lp->n = n;
+  lp->nnz = nnz;
+  lp->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  lp->precision = p->precision;
+  carve(lp, workspace, m, n, nnz, p->precision);
+  auto fail = [&](hlp_err e) {
+    delete lp;
+    return e;
+  };
+  // 1. row pointers, then the rows themselves
+  if (hipError_t e = launch_fill(reinterpret_cast<double*>(lp->flags), 0.0, 1, lp->stream); e != hipSuccess)
+    return fail(hip_fail(e, "fill"));
+  if (hipError_t e = launch_validate_rowptr(row_ptr, m, nnz, lp->flags, lp->stream); e != hipSuccess)
+    return fail(hip_fail(e, "validate_rowptr"));
+  int f = 0;
+  if (hlp_err e = read_flags(lp, &f); e != HLP_OK) return fail(e);
+  if (f) {
+    set_error(flag_message(f));
+    return fail(HLP_EINVAL);
+  }
+  if (hipError_t e = launch_validate_rows(row_ptr, col_idx, val, m, n, lp->flags, lp->stream); e != hipSuccess)
+    return fail(hip_fail(e, "validate_rows"));
+  if (hlp_err e = read_flags(lp, &f); e != HLP_OK) return fail(e);
+  if (f) {
+    set_error(flag_message(f));
+    return fail(HLP_EINVAL);
+  }
+  // 2. copy, transpose
+  if (hipError_t e = launch_copy_csr(row_ptr, col_idx, val, m, nnz, lp->rp, lp->col, lp->val0, lp->stream);
+      e != hipSuccess)
+    return fail(hip_fail(e, "copy_csr"));
+  lp->Lr = lanes_for(m ? (double)nnz / m : 1.0);
+  lp->Lc = lanes_for(n ? (double)nnz / n : 1.0);
+  if (hipError_t e = launch_transpose(lp); e != hipSuccess) return fail(hip_fail(e, "transpose"));
+  // 3. rescaling of A, then the vectors
+  if (hipError_t e = launch_rescale(lp, p->ruiz_iters, p->pock_chambolle); e != hipSuccess)
+    return fail(hip_fail(e, "rescale"));
+  if (hlp_err e = validate_and_scale_vectors(lp, c, lc, uc, lv, uv); e != HLP_OK) return fail(e);
+  // 4. stepsize
+  if (p->eta_override > 0.0) {
+    lp->eta = p->eta_override;
+    lp->power_iters = 0;
+  } else if (m == 0 || n == 0 || nnz == 0) {
+    lp->eta = 1.0;
+    lp->power_iters = 0;
+  } else {
+    PowerState ps{};
+    int first = 1;
+    while (true) {
+      if (hipError_t e = launch_power(lp, 16, first, p->power_max_iter, p->power_tol); e != hipSuccess)
+        return fail(hip_fail(e, "power"));
+      first = 0;
+      if (hipError_t e = hipMemcpyAsync(&ps, lp->pstate, sizeof(ps), hipMemcpyDeviceToHost, lp->stream);
+          e != hipSuccess)
+        return fail(hip_fail(e, "power readback"));
+      if (hipError_t e = hipStreamSynchronize(lp->stream); e != hipSuccess) return fail(hip_fail(e, "sync"));
+      if (ps.done) break;
+    }
+    lp->power_iters = ps.it;
+    lp->eta = ps.estimate > 0.0 ? 0.998 / ps.estimate : 1.0;
+  }
+  if (hipError_t e = hipStreamSynchronize(lp->stream); e != hipSuccess) return fail(hip_fail(e, "sync"));
+  lp->setup_s = now_s() - t0;
+  *out = lp;
+  return HLP_OK;
+}
+
+hlp_err hlp_lp_update_vectors(hlp_lp* lp, const double* c, const double* lc, const double* uc,
+                              const double* lv, const double* uv) {
+  if (!lp) {
+    set_error("NULL handle");
+    return HLP_EINVAL;
+  }
+  return validate_and_scale_vectors(lp, c, lc, uc, lv, uv);
+}
+
+hlp_err hlp_lp_scaling(const hlp_lp* lp, double* d_r, double* d_c, double* eta, int32_t* power_iters) {
+  if (!lp) {
+    set_error("NULL handle");
+    return HLP_EINVAL;
+  }
+  if (d_r && lp->m) HLP_HIP(hipMemcpyAsync(d_r, lp->dr, sizeof(double) * lp->m, hipMemcpyDeviceToDevice, lp->stream));
+  if (d_c && lp->n) HLP_HIP(hipMemcpyAsync(d_c, lp->dc, sizeof(double) * lp->n, hipMemcpyDeviceToDevice, lp->stream));
+  HLP_HIP(hipStreamSynchronize(lp->stream));
+  if (eta) *eta = lp->eta;
+  if (power_iters) *power_iters = lp->power_iters;
+  return HLP_OK;
+}
+
+hlp_err hlp_lp_transpose(const hlp_lp* lp, int32_t* col_ptr, int32_t* row_idx, double* val) {
+  if (!lp) {
+    set_error("NULL handle");
+    return HLP_EINVAL;
+  }
+  if (col_ptr)
+    HLP_HIP(hipMemcpyAsync(col_ptr, lp->cp, sizeof(int32_t) * ((size_t)lp->n + 1), hipMemcpyDeviceToDevice, lp->stream));
+  if (row_idx && lp->nnz)
+    HLP_HIP(hipMemcpyAsync(row_idx, lp->row, sizeof(int32_t) * lp->nnz, hipMemcpyDeviceToDevice, lp->stream));
+  if (val && lp->nnz)
+    HLP_HIP(hipMemcpyAsync(val, lp->tval, sizeof(double) * lp->nnz, hipMemcpyDeviceToDevice, lp->stream));
+  HLP_HIP(hipStreamSynchronize(lp->stream));
+  return HLP_OK;
+}
+
+void hlp_lp_destroy(hlp_lp* lp) { delete lp; }
+
+}  // extern "C"

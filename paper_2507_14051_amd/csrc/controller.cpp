@@ -1,0 +1,350 @@
+// Host controller: the iteration loop of restarted reflected Halpern PDHG
+// (paper Secs. 2.2 and 3) with the relative KKT termination test (Sec. 4), in
+// FP64 or in FP32 with iterative refinement.  All vector work runs in the HIP
+// kernels; the host only keeps the scalar state (omega, PID memory, k, T,
+// r0, r_prev) and reads ~13 reduced FP64 scalars once per check.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <limits>
+#include <vector>
+
+#include "hlp_internal.h"
+
+namespace hlp {
+
+namespace {
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+constexpr double kInf = std::numeric_limits<double>::infinity();
+
+// Controller state (Sec. 3): inner index k, total T, restart memory, PID memory.
+struct Ctl {
+  double omega = 1.0;
+  int64_t k = 0, t = 0, restarts = 0, checks = 0;
+  double r0 = kInf, r_prev = kInf;
+  double pid_sum = 0.0, e_prev = 0.0;
+  bool has_prev = false;
+};
+
+// r(z) = ||z - PDHG(z)||_P with P = [[omega/eta I, A^T], [A, 1/(eta omega) I]]
+double fixed_point_residual(const double* R, double eta, double omega) {
+  double q = (omega / eta) * R[Q_DX2] + 2.0 * R[Q_DYADX] + R[Q_DY2] / (eta * omega);
+  return std::sqrt(std::max(q, 0.0));
+}
+
+// Sec. 3, adaptive restart: sufficient decay, necessary decay + no local
+// progress, artificial restart (k and T after the increment).
+bool restart_test(double r, double r0, double r_prev, int64_t k, int64_t t, const hlp_params& p) {
+  return (r <= p.beta_sufficient * r0) || (r <= p.beta_necessary * r0 && r > r_prev) ||
+         ((double)k >= p.beta_artificial * (double)t);
+}
+
+// Sec. 3, primal weight update: PID control of log omega with the error
+// e = log(omega ||dx|| / ||dy||).
+double pid_update(double omega, double dxn, double dyn, Ctl& c, const hlp_params& p) {
+  if (!(dxn > p.pid_min_norm && dyn > p.pid_min_norm)) return omega;
+  const double e = std::log(omega * dxn / dyn);
+  c.pid_sum += e;
+  const double de = c.has_prev ? e - c.e_prev : 0.0;
+  c.e_prev = e;
+  c.has_prev = true;
+  return std::exp(std::log(omega) - (p.kp * e + p.ki * c.pid_sum + p.kd * de));
+}
+
+// Power of two for the refinement scale: 2^floor(log2(1/delta)) within [1, min(2^12 prev, 2^40)].
+double pow2_scale(double delta, double prev) {
+  const double cap = std::min(prev * 4096.0, std::ldexp(1.0, 40));
+  if (!(delta > 0.0) || !std::isfinite(delta)) return cap;
+  const double s = std::ldexp(1.0, (int)std::floor(std::log2(1.0 / delta)));
+  return std::min(std::max(s, 1.0), cap);
+}
+
+struct Kkt {
+  double pobj, dobj, rel_gap, rel_p, rel_d, rel;
+  bool finite;
+};
+
+Kkt kkt_from(const double* R, const hlp_lp* lp) {
+  Kkt k{};
+  k.pobj = R[Q_POBJ];
+  k.dobj = R[Q_DOBJ_R] + R[Q_DOBJ_C];
+  const double rho_p = std::sqrt(std::max(R[Q_RP2], 0.0));
+  const double rho_d = std::sqrt(std::max(R[Q_RD2], 0.0));
+  k.rel_gap = std::fabs(k.pobj - k.dobj) / (1.0 + std::fabs(k.pobj) + std::fabs(k.dobj));
+  k.rel_p = rho_p / (1.0 + lp->norm_b);
+  k.rel_d = rho_d / (1.0 + lp->norm_c);
+  k.rel = std::max(k.rel_gap, std::max(k.rel_p, k.rel_d));
+  k.finite = std::isfinite(k.pobj) && std::isfinite(k.dobj) && std::isfinite(rho_p) && std::isfinite(rho_d);
+  return k;
+}
+
+hlp_err check_params(const hlp_params* p) {
+  if (!p) return HLP_OK;
+  if (p->max_iter < 1 || p->eval_freq < 1 || !(p->tol >= 0.0) || !(p->gamma >= 0.0 && p->gamma <= 1.0) ||
+      !(p->omega0 > 0.0) || !std::isfinite(p->omega0) || p->trace_iters < 0 || !(p->time_limit_s >= 0.0)) {
+    set_error("bad parameters: need max_iter >= 1, eval_freq >= 1, tol >= 0, gamma in [0,1], omega0 > 0, "
+              "trace_iters >= 0, time_limit_s >= 0");
+    return HLP_EINVAL;
+  }
+  return HLP_OK;
+}
+
+hlp_err read_results(hlp_lp* lp, double* R) {
+  HLP_HIP(hipMemcpyAsync(R, lp->results, sizeof(double) * NSLOT * NQ, hipMemcpyDeviceToHost, lp->stream));
+  HLP_HIP(hipStreamSynchronize(lp->stream));
+  return HLP_OK;
+}
+
+#define HLP_K(call)                                  \
+  do {                                               \
+    hipError_t e_ = (call);                          \
+    if (e_ != hipSuccess) return hip_fail(e_, #call); \
+  } while (0)
+
+// ------------------------------------------------------------------ the FP64 loop
+hlp_err solve_fp64(hlp_lp* lp, const hlp_params& p, const double* x0, const double* y0, double* rout,
+                   double* trace, Ctl& c, Kkt& kk, int32_t& status) {
+  const double eta = lp->eta;
+  const int64_t tstride = 2 * (int64_t)lp->n + 2 * (int64_t)lp->m;
+  HLP_K(launch_warm_start(lp, x0, y0));
+  c.omega = p.omega0;
+  bool r0_pending = false;
+  double R[NSLOT * NQ];
+  const double t_start = now_s();
+  while (true) {
+    const double tau = eta / c.omega, sigma = eta * c.omega;
+    const bool check = ((c.t + 1) % p.eval_freq == 0) || (c.t + 1 == p.max_iter);
+    const bool need_r = (c.k == 0) || check;
+    const bool traced = trace && c.t < p.trace_iters;
+    StepArgs s{tau, sigma, (double)(c.k + 1) / (double)(c.k + 2), p.gamma, (need_r || traced) ? 1 : 0, 0};
+    HLP_K(launch_primal(lp, s));
+    HLP_K(launch_dual(lp, s));
+    if (need_r) {
+      HLP_K(launch_finalize(lp, 1 | 2, check ? SLOT_CHECK : SLOT_R0));
+      if (!check) r0_pending = true;
+    }
+    if (traced) HLP_K(launch_trace(lp, trace + c.t * tstride));
+    const bool epoch_start = c.k == 0;
+    ++c.k;
+    ++c.t;
+    if (p.debug_poison_iter > 0 && c.t == p.debug_poison_iter) HLP_K(launch_poison(lp));
+    if (!check) continue;
+    HLP_K(launch_kkt_cols(lp, SLOT_CHECK, rout));
+    HLP_K(launch_finalize(lp, 4, SLOT_CHECK));
+    HLP_TRY(read_results(lp, R));
+    ++c.checks;
+    const double* RC = R + SLOT_CHECK * NQ;
+    const double r = fixed_point_residual(RC, eta, c.omega);
+    if (epoch_start) {
+      c.r0 = r;
+    } else if (r0_pending) {
+      c.r0 = fixed_point_residual(R + SLOT_R0 * NQ, eta, c.omega);
+    }
+    r0_pending = false;
+    kk = kkt_from(RC, lp);
+    status = -1;
+    if (!kk.finite || !std::isfinite(r)) status = HLP_NUMERICAL;
+    else if (kk.rel <= p.tol) status = HLP_OPTIMAL;
+    else if (c.t >= p.max_iter) status = HLP_ITER_LIMIT;
+    else if (now_s() - t_start >= p.time_limit_s) status = HLP_TIME_LIMIT;
+    if (status >= 0) return HLP_OK;
+    if (restart_test(r, c.r0, c.r_prev, c.k, c.t, p)) {
+      ++c.restarts;
+      c.omega = pid_update(c.omega, std::sqrt(RC[Q_XA2]), std::sqrt(RC[Q_YA2]), c, p);
+      HLP_K(launch_restart_copy(lp, p.restart_to_current));
+      c.k = 0;
+      c.r_prev = kInf;
+    } else {
+      c.r_prev = r;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ FP32 loop with refinement
+// Iterates and anchors are FP32 corrections around an FP64 centre:
+// x = xc + x'/P, y = yc + y'/D.  At every restart the centre moves to zhat
+// (FP64), P and D are recomputed from the FP64 violations and the FP32
+// correction data are rebuilt; the iteration is the same PDHG step with
+// tau' = tau P / D and sigma' = sigma D / P.
+hlp_err solve_mixed(hlp_lp* lp, const hlp_params& p, const double* x0, const double* y0, double* rout,
+                    double* trace, Ctl& c, Kkt& kk, int32_t& status) {
+  const double eta = lp->eta;
+  const int64_t tstride = 2 * (int64_t)lp->n + 2 * (int64_t)lp->m;
+  // centre at the start point
+  HLP_K(launch_warm_start(lp, x0, y0));
+  if (lp->n) HLP_HIP(hipMemcpyAsync(lp->xh, lp->x, sizeof(double) * lp->n, hipMemcpyDeviceToDevice, lp->stream));
+  if (lp->m) HLP_HIP(hipMemcpyAsync(lp->yh, lp->y, sizeof(double) * lp->m, hipMemcpyDeviceToDevice, lp->stream));
+  HLP_K(launch_kkt_rows(lp, SLOT_TMP));
+  HLP_K(launch_kkt_cols(lp, SLOT_TMP, nullptr));
+  double P = 1.0, D = 1.0;
+  HLP_K(launch_recentre(lp, P, D));
+  c.omega = p.omega0;  // original units; the FP32 step uses omega' = omega D / P
+  bool r0_pending = false;
+  double R[NSLOT * NQ];
+  const double t_start = now_s();
+  while (true) {
+    const double om = c.omega * D / P;
+    const double tau = eta / om, sigma = eta * om;
+    const bool check = ((c.t + 1) % p.eval_freq == 0) || (c.t + 1 == p.max_iter);
+    const bool need_r = (c.k == 0) || check;
+    const bool traced = trace && c.t < p.trace_iters;
+    StepArgs s{tau, sigma, (double)(c.k + 1) / (double)(c.k + 2), p.gamma, (need_r || traced) ? 1 : 0, 0};
+    HLP_K(launch_primal32(lp, s));
+    HLP_K(launch_dual32(lp, s));
+    if (need_r) {
+      HLP_K(launch_finalize(lp, 1 | 2 | 16, check ? SLOT_CHECK : SLOT_R0));
+      if (!check) r0_pending = true;
+    }
+    if (traced) HLP_K(launch_trace32(lp, trace + c.t * tstride, P, D));
+    const bool epoch_start = c.k == 0;
+    ++c.k;
+    ++c.t;
+    if (!check) continue;
+    HLP_K(launch_combine(lp, P, D));
+    HLP_K(launch_kkt_rows(lp, SLOT_CHECK));
+    HLP_K(launch_kkt_cols(lp, SLOT_CHECK, rout));
+    HLP_K(launch_finalize(lp, 4 | 8, SLOT_CHECK));
+    HLP_TRY(read_results(lp, R));
+    ++c.checks;
+    const double* RC = R + SLOT_CHECK * NQ;
+    const double r = fixed_point_residual(RC, eta, om);
+    if (epoch_start) {
+      c.r0 = r;
+    } else if (r0_pending) {
+      c.r0 = fixed_point_residual(R + SLOT_R0 * NQ, eta, om);
+    }
+    r0_pending = false;
+    kk = kkt_from(RC, lp);
+    status = -1;
+    if (!kk.finite || !std::isfinite(r)) status = HLP_NUMERICAL;
+    else if (kk.rel <= p.tol) status = HLP_OPTIMAL;
+    else if (c.t >= p.max_iter) status = HLP_ITER_LIMIT;
+    else if (now_s() - t_start >= p.time_limit_s) status = HLP_TIME_LIMIT;
+    if (status >= 0) return HLP_OK;
+    if (restart_test(r, c.r0, c.r_prev, c.k, c.t, p)) {
+      ++c.restarts;
+      const double om_new = pid_update(om, std::sqrt(RC[Q_XA2]), std::sqrt(RC[Q_YA2]), c, p);
+      c.omega = om_new * P / D;
+      // refinement: re-centre at zhat and rescale from the FP64 violations there
+      P = pow2_scale(std::max(RC[Q_VP], RC[Q_VX]), P);
+      D = pow2_scale(RC[Q_VD], D);
+      HLP_K(launch_recentre(lp, P, D));
+      c.k = 0;
+      c.r_prev = kInf;
+    } else {
+      c.r_prev = r;
+    }
+  }
+}
+
+}  // namespace
+
+}  // namespace hlp
+
+using namespace hlp;
+
+extern "C" {
+
+hlp_err hlp_solve(hlp_lp* lp, const hlp_params* pp, const double* x0, const double* y0, double* x,
+                  double* y, double* r, hlp_info* info, double* trace) {
+  if (!lp) {
+    set_error("hlp_solve: NULL handle");
+    return HLP_EINVAL;
+  }
+  hlp_params p;
+  hlp_params_default(&p);
+  if (pp) p = *pp;
+  HLP_TRY(check_params(&p));
+  if (p.precision != lp->precision) {
+    set_error("hlp_solve: precision differs from the one the handle was created with");
+    return HLP_EUNSUPPORTED;
+  }
+  const double t0 = now_s();
+  Ctl c;
+  Kkt kk{};
+  int32_t status = -1;
+  hlp_err e = p.precision == HLP_MIXED ? solve_mixed(lp, p, x0, y0, r, trace, c, kk, status)
+                                       : solve_fp64(lp, p, x0, y0, r, trace, c, kk, status);
+  if (e != HLP_OK) return e;
+  HLP_HIP(launch_unscale(lp, x, y));
+  HLP_HIP(hipStreamSynchronize(lp->stream));
+  if (info) {
+    info->status = status;
+    info->power_iters = lp->power_iters;
+    info->iters = c.t;
+    info->restarts = c.restarts;
+    info->checks = c.checks;
+    info->rel_kkt = kk.rel;
+    info->rel_gap = kk.rel_gap;
+    info->rel_primal = kk.rel_p;
+    info->rel_dual = kk.rel_d;
+    info->pobj = kk.pobj;
+    info->dobj = kk.dobj;
+    info->omega = c.omega;
+    info->eta = lp->eta;
+    info->setup_s = lp->setup_s;
+    info->solve_s = now_s() - t0;
+  }
+  return HLP_OK;
+}
+
+hlp_err hlp_profile_iterations(hlp_lp* lp, const hlp_params* pp, int32_t iters, double* ms_out) {
+  if (!lp || !ms_out || iters < 1) {
+    set_error("hlp_profile_iterations: NULL handle/output or iters < 1");
+    return HLP_EINVAL;
+  }
+  hlp_params p;
+  hlp_params_default(&p);
+  if (pp) p = *pp;
+  const bool mixed = p.precision == HLP_MIXED;
+  if (mixed && lp->precision != HLP_MIXED) {
+    set_error("hlp_profile_iterations: the handle holds no FP32 mirror");
+    return HLP_EUNSUPPORTED;
+  }
+  HLP_HIP(launch_warm_start(lp, nullptr, nullptr));
+  if (mixed) {
+    if (lp->n) HLP_HIP(hipMemcpyAsync(lp->xh, lp->x, sizeof(double) * lp->n, hipMemcpyDeviceToDevice, lp->stream));
+    if (lp->m) HLP_HIP(hipMemcpyAsync(lp->yh, lp->y, sizeof(double) * lp->m, hipMemcpyDeviceToDevice, lp->stream));
+    HLP_HIP(launch_kkt_rows(lp, SLOT_TMP));
+    HLP_HIP(launch_kkt_cols(lp, SLOT_TMP, nullptr));
+    HLP_HIP(launch_recentre(lp, 1.0, 1.0));
+  }
+  std::vector<hipEvent_t> ev(2 * (size_t)iters + 1);
+  for (auto& e : ev) HLP_HIP(hipEventCreate(&e));
+  const double eta = lp->eta, om = p.omega0;
+  HLP_HIP(hipEventRecord(ev[0], lp->stream));
+  for (int32_t i = 0; i < iters; ++i) {
+    StepArgs s{eta / om, eta * om, (double)(i + 1) / (double)(i + 2), p.gamma, 0, 0};
+    HLP_HIP(mixed ? launch_primal32(lp, s) : launch_primal(lp, s));
+    HLP_HIP(hipEventRecord(ev[2 * i + 1], lp->stream));
+    HLP_HIP(mixed ? launch_dual32(lp, s) : launch_dual(lp, s));
+    HLP_HIP(hipEventRecord(ev[2 * i + 2], lp->stream));
+  }
+  HLP_HIP(hipStreamSynchronize(lp->stream));
+  double tp = 0.0, td = 0.0, tot = 0.0;
+  for (int32_t i = 0; i < iters; ++i) {
+    float a = 0.f, b = 0.f;
+    HLP_HIP(hipEventElapsedTime(&a, ev[2 * i], ev[2 * i + 1]));
+    HLP_HIP(hipEventElapsedTime(&b, ev[2 * i + 1], ev[2 * i + 2]));
+    tp += a;
+    td += b;
+  }
+  float all = 0.f;
+  HLP_HIP(hipEventElapsedTime(&all, ev[0], ev[2 * (size_t)iters]));
+  tot = all;
+  for (auto& e : ev) hipEventDestroy(e);
+  ms_out[0] = tp / iters;
+  ms_out[1] = td / iters;
+  ms_out[2] = tot / iters;
+  ms_out[3] = iters;
+  return HLP_OK;
+}
+
+}  // extern "C"

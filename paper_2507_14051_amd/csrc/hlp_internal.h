@@ -1,0 +1,181 @@
+// Internal declarations shared by the host controller and the kernel files.
+// Host-side only: no device code here.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/hlp.h"
+
+namespace hlp {
+
+// Quantities reduced at a check.  The primal and dual half-steps in their
+// "residual" variants and the transpose KKT kernel each write per-block
+// partial sums of their own subset; finalize kernels sum them in block order.
+enum Q : int {
+  Q_DX2 = 0,     // ||x - xhat||^2                       (primal kernel)
+  Q_XA2 = 1,     // ||xhat - x0||^2                      (primal kernel, PID)
+  Q_DY2 = 2,     // ||y - yhat||^2                       (dual kernel)
+  Q_DYADX = 3,   // (y - yhat)^T A~ (x - xhat)           (dual kernel)
+  Q_YA2 = 4,     // ||yhat - y0||^2                      (dual kernel, PID)
+  Q_RP2 = 5,     // ||A x - proj(A x)||^2, unscaled      (dual kernel)
+  Q_DOBJ_R = 6,  // row part of the dual objective       (dual kernel)
+  Q_RD2 = 7,     // ||g - proj_R(g)||^2, unscaled        (transpose KKT kernel)
+  Q_DOBJ_C = 8,  // column part of the dual objective    (transpose KKT kernel)
+  Q_POBJ = 9,    // c^T x                                (transpose KKT kernel)
+  Q_VP = 10,     // max primal violation, scaled space    (mixed: dual kernel; max)
+  Q_VD = 11,     // max dual violation, scaled space      (mixed: KKT kernel; max)
+  Q_VX = 12,     // max bound violation of x, scaled      (mixed: KKT kernel; max)
+  NQ = 13
+};
+
+// Result slots (each NQ doubles) in the device results array.
+enum Slot : int { SLOT_CHECK = 0, SLOT_R0 = 1, SLOT_TMP = 2, NSLOT = 3 };
+
+// Power-iteration state kept on the device.
+struct PowerState {
+  double s;          // ||A~^T A~ v|| of the last pass
+  double root;       // sqrt(s)
+  double prev_root;
+  double estimate;   // final ||A~||_2 estimate
+  int32_t it;        // passes done
+  int32_t done;
+  int32_t has_prev;
+  int32_t pad;
+};
+
+}  // namespace hlp
+
+struct hlp_lp {
+  int32_t m = 0, n = 0;
+  int64_t nnz = 0;
+  hipStream_t stream = nullptr;
+  int32_t precision = HLP_FP64;
+  // CSR of A~ (scaled) and its explicit transpose
+  int32_t *rp = nullptr, *col = nullptr;
+  double* val = nullptr;
+  float* val32 = nullptr;
+  int32_t *cp = nullptr, *row = nullptr;
+  double* tval = nullptr;
+  float* tval32 = nullptr;
+  double* val0 = nullptr;   // unscaled CSR values (kept to rescale after a vector update? no: for stats)
+  double* tval0 = nullptr;  // unscaled transpose values
+  int32_t Lr = 8, Lc = 8;   // lanes per row for A~ and A~^T
+  // scaling diagonals and scaled vectors
+  double *dr = nullptr, *dc = nullptr;
+  double *ct = nullptr, *lct = nullptr, *uct = nullptr, *lvt = nullptr, *uvt = nullptr;
+  double norm_c = 0.0, norm_b = 0.0;  // ||c||_2 and ||(lc,uc) finite||_2, original space
+  double eta = 1.0;
+  int32_t power_iters = 0;
+  // FP64 iteration state
+  double *x = nullptr, *y = nullptr, *xa = nullptr, *ya = nullptr, *xbar = nullptr;
+  double *xh = nullptr, *yh = nullptr, *dxv = nullptr, *rbuf = nullptr;
+  // FP32 iteration state (mixed precision) and FP64 centre
+  float *x32 = nullptr, *y32 = nullptr, *xa32 = nullptr, *ya32 = nullptr, *xbar32 = nullptr;
+  float *xh32 = nullptr, *yh32 = nullptr, *dx32 = nullptr;
+  float *c32 = nullptr, *lv32 = nullptr, *uv32 = nullptr, *lc32 = nullptr, *uc32 = nullptr,
+        *b32 = nullptr;
+  double *xcen = nullptr, *ycen = nullptr, *axc = nullptr, *atyc = nullptr;
+  // reductions
+  double* partials = nullptr;
+  int64_t partial_blocks = 0;  // capacity in blocks (each NQ doubles)
+  double* results = nullptr;   // NSLOT * NQ
+  hlp::PowerState* pstate = nullptr;
+  int32_t* flags = nullptr;
+  // setup scratch (transpose)
+  int32_t *kA = nullptr, *kB = nullptr, *vA = nullptr, *vB = nullptr, *rowof = nullptr;
+  int32_t *hist = nullptr, *scan_tmp = nullptr;
+  int64_t hist_len = 0, scan_tmp_len = 0;
+  double* pv = nullptr;  // power iteration vectors (aliases)
+  double* pu = nullptr;
+  double* pw = nullptr;
+  double setup_s = 0.0;
+};
+
+namespace hlp {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+hlp_err hip_fail(hipError_t e, const char* what);
+#define HLP_HIP(call)                                         \
+  do {                                                        \
+    hipError_t e_ = (call);                                   \
+    if (e_ != hipSuccess) return ::hlp::hip_fail(e_, #call);  \
+  } while (0)
+#define HLP_TRY(call)                   \
+  do {                                  \
+    hlp_err r_ = (call);                \
+    if (r_ != HLP_OK) return r_;        \
+  } while (0)
+
+// ---------------------------------------------------------------- layout
+// Carve the workspace.  With lp->... == nullptr base, only computes the size.
+size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t precision);
+
+int lanes_for(double mean_row_len);
+
+// ---------------------------------------------------------------- kernel launchers (kernels_*.hip)
+// Validation: returns bit flags through *flags (device), see kernels_setup.hip.
+hipError_t launch_validate_rowptr(const int64_t* rp, int32_t m, int64_t nnz, int32_t* flags, hipStream_t s);
+hipError_t launch_validate_rows(const int64_t* rp, const int32_t* col, const double* val, int32_t m,
+                                int32_t n, int32_t* flags, hipStream_t s);
+hipError_t launch_validate_vectors(const double* c, const double* lc, const double* uc,
+                                   const double* lv, const double* uv, int32_t m, int32_t n,
+                                   int32_t* flags, hipStream_t s);
+hipError_t launch_copy_csr(const int64_t* rp64, const int32_t* col, const double* val, int32_t m,
+                           int64_t nnz, int32_t* rp, int32_t* col_out, double* val_out, hipStream_t s);
+hipError_t launch_transpose(hlp_lp* lp);
+hipError_t launch_rescale(hlp_lp* lp, int32_t ruiz_iters, int32_t pock_chambolle);
+hipError_t launch_scale_vectors(hlp_lp* lp, const double* c, const double* lc, const double* uc,
+                                const double* lv, const double* uv);
+hipError_t launch_power(hlp_lp* lp, int32_t passes, int32_t first_pass, int32_t max_iter, double tol);
+hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t s);
+hipError_t launch_fill32(float* p, float v, int64_t n, hipStream_t s);
+hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+
+// Iteration (kernels_iter.hip).
+struct StepArgs {
+  double tau, sigma, a, gamma;
+  int32_t residual;   // compute the check quantities and write xhat / yhat
+  int32_t slot;       // result slot for the finalize
+};
+hipError_t launch_primal(hlp_lp* lp, const StepArgs& s);
+hipError_t launch_dual(hlp_lp* lp, const StepArgs& s);
+hipError_t launch_kkt_cols(hlp_lp* lp, int32_t slot, double* r_out);
+hipError_t launch_finalize(hlp_lp* lp, int32_t which /*0 primal,1 dual,2 kkt*/, int32_t slot);
+hipError_t launch_restart_copy(hlp_lp* lp, int32_t to_current);
+hipError_t launch_warm_start(hlp_lp* lp, const double* x0, const double* y0);
+hipError_t launch_unscale(hlp_lp* lp, double* x, double* y);
+hipError_t launch_trace(hlp_lp* lp, double* dst);
+hipError_t launch_poison(hlp_lp* lp);
+
+// Mixed precision (kernels_iter.hip).
+hipError_t launch_primal32(hlp_lp* lp, const StepArgs& s);
+hipError_t launch_dual32(hlp_lp* lp, const StepArgs& s);
+hipError_t launch_combine(hlp_lp* lp, double P, double D);  // xh <- xcen + xh32/P, yh <- ...
+hipError_t launch_kkt_rows(hlp_lp* lp, int32_t slot);        // A~ xh (FP64) and row KKT terms
+hipError_t launch_recentre(hlp_lp* lp, double P, double D);  // rebuild the correction data
+hipError_t launch_zero_mixed(hlp_lp* lp);
+hipError_t launch_trace32(hlp_lp* lp, double* dst, double P, double D);
+
+// Adjoint (kernels_adjoint.hip).
+struct AdjStep {
+  double tau, sigma, a, gamma;
+  int32_t mode;  // 0: Halpern step; 1: restart after the step; 2: last iteration (output)
+};
+hipError_t launch_fwd_masks(hlp_lp* lp, const StepArgs& s, uint8_t* mx, uint8_t* my);
+hipError_t launch_bwd_init(hlp_lp* lp, const double* gx, const double* gy, double* adj, const AdjStep& st,
+                           const uint8_t* my);
+hipError_t launch_bwd_cols(hlp_lp* lp, double* adj, const AdjStep& st, const uint8_t* mx);
+hipError_t launch_bwd_rows(hlp_lp* lp, double* adj, const AdjStep& st, const AdjStep& prev,
+                           const uint8_t* my_prev, int32_t has_prev);
+hipError_t launch_bwd_out(hlp_lp* lp, const double* adj, double* gc, double* glc, double* guc,
+                          double* glv, double* guv);
+
+// Profiling helpers
+hipError_t launch_copy_state(hlp_lp* lp, double* dst, const double* src, int64_t n);
+
+}  // namespace hlp

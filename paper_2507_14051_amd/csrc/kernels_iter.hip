@@ -1,0 +1,654 @@
+// Hot-loop kernels of restarted reflected Halpern PDHG (paper Secs. 2.2, 3).
+//
+// One iteration is two launches:
+//   primal half-step: g = A~^T y over the explicit transpose (L lanes per
+//     column), fused with xhat = clamp(x - tau (c~ - g), lv~, uv~),
+//     xbar = 2 xhat - x and the reflected Halpern update of x;
+//   dual half-step: h = A~ xbar over the CSR (L lanes per row), fused with
+//     w = h - y/sigma, yhat = sigma (clamp(w, lc~, uc~) - w) and the reflected
+//     Halpern update of y.
+// Their "residual" variants also write xhat, yhat, x - xhat and per-block
+// partial sums of the check quantities (fixed-point residual in the P-norm of
+// Sec. 2.2, the PID distances, the row side of the KKT error of Sec. 4).  A
+// transpose kernel adds the column side of the KKT error.  All reductions are
+// per-block partials summed in block order: results are bit-reproducible.
+#include <cmath>
+
+#include "device.h"
+#include "hlp_internal.h"
+
+namespace hlp {
+
+namespace {
+
+inline int nblocks(int64_t threads) { return (int)((threads + kBlock - 1) / kBlock); }
+
+// partial regions inside lp->partials, each `cap` blocks x 8 doubles
+constexpr int kRegionStride = 8;
+inline double* region(hlp_lp* lp, int r) { return lp->partials + (int64_t)r * lp->partial_blocks * kRegionStride; }
+enum { R_PRIMAL = 0, R_DUAL = 1, R_KKT = 2, R_ROWS = 3 };
+
+// ============================================================================ FP64
+struct PrimalArgs {
+  const int32_t* cp; const int32_t* row; const double* tval;
+  const double* y; double* x; const double* xa; const double* ct; const double* lv; const double* uv;
+  double* xbar; double* xh; double* dx; double* partials;
+  int32_t n; double tau, a, gamma;
+};
+
+template <int L, bool RES>
+__global__ __launch_bounds__(kBlock) void k_primal(PrimalArgs p) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t j = t / L;
+  const int lane = threadIdx.x & (L - 1);
+  const double* __restrict__ tval = p.tval;
+  const int32_t* __restrict__ row = p.row;
+  const double* __restrict__ y = p.y;
+  double acc = 0.0;
+  if (j < p.n) {
+    const int s = p.cp[j], e = p.cp[j + 1];
+    for (int q = s + lane; q < e; q += L) acc += tval[q] * y[row[q]];
+  }
+  acc = group_sum<L>(acc);
+  double q0 = 0.0, q1 = 0.0;
+  if (j < p.n && lane == 0) {
+    const double xj = p.x[j];
+    const double v = xj - p.tau * (p.ct[j] - acc);
+    const double xh = clampv(v, p.lv[j], p.uv[j]);
+    p.xbar[j] = 2.0 * xh - xj;
+    const double xaj = p.xa[j];
+    p.x[j] = p.a * ((1.0 + p.gamma) * xh - p.gamma * xj) + (1.0 - p.a) * xaj;
+    if (RES) {
+      p.xh[j] = xh;
+      const double d = xj - xh;
+      p.dx[j] = d;
+      q0 = d * d;
+      const double e = xh - xaj;
+      q1 = e * e;
+    }
+  }
+  if (RES) {
+    double v[2] = {q0, q1};
+    block_reduce_store<2>(v, p.partials + (int64_t)blockIdx.x * kRegionStride);
+  }
+}
+
+struct DualArgs {
+  const int32_t* rp; const int32_t* col; const double* val;
+  const double* xbar; const double* dx; const double* xh;
+  double* y; const double* ya; const double* lc; const double* uc; const double* dr;
+  double* yh; double* partials;
+  int32_t m; double sigma, a, gamma;
+};
+
+template <int L, bool RES>
+__global__ __launch_bounds__(kBlock) void k_dual(DualArgs p) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = t / L;
+  const int lane = threadIdx.x & (L - 1);
+  const double* __restrict__ val = p.val;
+  const int32_t* __restrict__ col = p.col;
+  const double* __restrict__ xbar = p.xbar;
+  double acc = 0.0, adx = 0.0, axh = 0.0;
+  if (i < p.m) {
+    const int s = p.rp[i], e = p.rp[i + 1];
+    for (int q = s + lane; q < e; q += L) {
+      const double v = val[q];
+      const int c = col[q];
+      acc += v * xbar[c];
+      if (RES) {
+        adx += v * p.dx[c];
+        axh += v * p.xh[c];
+      }
+    }
+  }
+  acc = group_sum<L>(acc);
+  if (RES) {
+    adx = group_sum<L>(adx);
+    axh = group_sum<L>(axh);
+  }
+  double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (i < p.m && lane == 0) {
+    const double yi = p.y[i];
+    const double lo = p.lc[i], hi = p.uc[i];
+    const double w = acc - yi / p.sigma;
+    const double yh = p.sigma * (clampv(w, lo, hi) - w);
+    const double yai = p.ya[i];
+    p.y[i] = p.a * ((1.0 + p.gamma) * yh - p.gamma * yi) + (1.0 - p.a) * yai;
+    if (RES) {
+      p.yh[i] = yh;
+      const double dy = yi - yh;
+      q[0] = dy * dy;
+      q[1] = dy * adx;
+      const double e = yh - yai;
+      q[2] = e * e;
+      const double pr = (axh - clampv(axh, lo, hi)) / p.dr[i];
+      q[3] = pr * pr;
+      q[4] = (finite(lo) ? lo * fmax(yh, 0.0) : 0.0) - (finite(hi) ? hi * fmax(-yh, 0.0) : 0.0);
+    }
+  }
+  if (RES) block_reduce_store<5>(q, p.partials + (int64_t)blockIdx.x * kRegionStride);
+}
+
+// Column side of the KKT error at (xhat, yhat): g~ = c~ - A~^T yhat,
+// r~ = proj_R(g~), ||(g~ - r~)/d_c||^2, the column part of the dual objective,
+// c~^T xhat; in mixed mode also the max dual violation |g~ - r~| and the max
+// bound violation of xhat (scaled space), and A~^T yhat itself.
+struct KktColArgs {
+  const int32_t* cp; const int32_t* row; const double* tval;
+  const double* yh; const double* xh; const double* ct; const double* lv; const double* uv;
+  const double* dc; double* r_out; double* aty_out; double* partials;
+  int32_t n;
+};
+
+template <int L, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_kkt_cols(KktColArgs p) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t j = t / L;
+  const int lane = threadIdx.x & (L - 1);
+  double acc = 0.0;
+  if (j < p.n) {
+    const int s = p.cp[j], e = p.cp[j + 1];
+    for (int q = s + lane; q < e; q += L) acc += p.tval[q] * p.yh[p.row[q]];
+  }
+  acc = group_sum<L>(acc);
+  double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (j < p.n && lane == 0) {
+    const double g = p.ct[j] - acc;
+    const double lo = p.lv[j], hi = p.uv[j];
+    const bool fl = finite(lo), fu = finite(hi);
+    const double r = (fl && fu) ? g : (fl ? fmax(g, 0.0) : (fu ? fmin(g, 0.0) : 0.0));
+    const double d = p.dc[j];
+    const double e = (g - r) / d;
+    q[0] = e * e;
+    q[1] = (fl ? lo * fmax(r, 0.0) : 0.0) - (fu ? hi * fmax(-r, 0.0) : 0.0);
+    const double xj = p.xh[j];
+    q[2] = p.ct[j] * xj;
+    if (p.r_out) p.r_out[j] = r / d;
+    if (MIXED) {
+      q[3] = fabs(g - r);
+      q[4] = fabs(xj - clampv(xj, lo, hi));
+      p.aty_out[j] = acc;
+    }
+  }
+  if constexpr (MIXED) {
+    block_reduce_store<5>(q, p.partials + (int64_t)blockIdx.x * kRegionStride, 8u | 16u);
+  } else {
+    double q3[3] = {q[0], q[1], q[2]};
+    block_reduce_store<3>(q3, p.partials + (int64_t)blockIdx.x * kRegionStride);
+  }
+}
+
+// Row side of the KKT error for a point given in FP64 (mixed mode):
+// A~ xh, ||(A~xh - proj)/d_r||^2, the row dual-objective part, the max
+// primal violation (scaled); stores A~ xh.
+struct KktRowArgs {
+  const int32_t* rp; const int32_t* col; const double* val;
+  const double* xh; const double* yh; const double* lc; const double* uc; const double* dr;
+  double* ax_out; double* partials;
+  int32_t m;
+};
+
+template <int L>
+__global__ __launch_bounds__(kBlock) void k_kkt_rows(KktRowArgs p) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = t / L;
+  const int lane = threadIdx.x & (L - 1);
+  double acc = 0.0;
+  if (i < p.m) {
+    const int s = p.rp[i], e = p.rp[i + 1];
+    for (int q = s + lane; q < e; q += L) acc += p.val[q] * p.xh[p.col[q]];
+  }
+  acc = group_sum<L>(acc);
+  double q[3] = {0.0, 0.0, 0.0};
+  if (i < p.m && lane == 0) {
+    const double lo = p.lc[i], hi = p.uc[i];
+    const double viol = acc - clampv(acc, lo, hi);
+    const double pr = viol / p.dr[i];
+    q[0] = pr * pr;
+    const double yh = p.yh[i];
+    q[1] = (finite(lo) ? lo * fmax(yh, 0.0) : 0.0) - (finite(hi) ? hi * fmax(-yh, 0.0) : 0.0);
+    q[2] = fabs(viol);
+    p.ax_out[i] = acc;
+  }
+  block_reduce_store<3>(q, p.partials + (int64_t)blockIdx.x * kRegionStride, 4u);
+}
+
+// ============================================================================ FP32 (mixed)
+// Shifted coordinates x = xc + x'/P, y = yc + y'/D; the step on (x', y') is
+// the same PDHG step with tau' = tau P/D, sigma' = sigma D/P and data
+// (c', lv', uv', lc', uc', b):  yhat' = y' + sigma'(clamp(h - (b + y')/sigma') - h).
+struct Primal32Args {
+  const int32_t* cp; const int32_t* row; const float* tval;
+  const float* y; float* x; const float* xa; const float* c; const float* lv; const float* uv;
+  float* xbar; float* xh; float* dx; double* partials;
+  int32_t n; float tau, a, gamma;
+};
+
+template <int L, bool RES>
+__global__ __launch_bounds__(kBlock) void k_primal32(Primal32Args p) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t j = t / L;
+  const int lane = threadIdx.x & (L - 1);
+  float acc = 0.0f;
+  if (j < p.n) {
+    const int s = p.cp[j], e = p.cp[j + 1];
+    for (int q = s + lane; q < e; q += L) acc += p.tval[q] * p.y[p.row[q]];
+  }
+  acc = group_sum<L>(acc);
+  double q0 = 0.0, q1 = 0.0;
+  if (j < p.n && lane == 0) {
+    const float xj = p.x[j];
+    const float v = xj - p.tau * (p.c[j] - acc);
+    const float xh = clampv(v, p.lv[j], p.uv[j]);
+    p.xbar[j] = 2.0f * xh - xj;
+    const float xaj = p.xa[j];
+    p.x[j] = p.a * ((1.0f + p.gamma) * xh - p.gamma * xj) + (1.0f - p.a) * xaj;
+    if (RES) {
+      p.xh[j] = xh;
+      const float d = xj - xh;
+      p.dx[j] = d;
+      q0 = (double)d * (double)d;
+      const double e = (double)(xh - xaj);
+      q1 = e * e;
+    }
+  }
+  if (RES) {
+    double v[2] = {q0, q1};
+    block_reduce_store<2>(v, p.partials + (int64_t)blockIdx.x * kRegionStride);
+  }
+}
+
+struct Dual32Args {
+  const int32_t* rp; const int32_t* col; const float* val;
+  const float* xbar; const float* dx;
+  float* y; const float* ya; const float* lc; const float* uc; const float* b;
+  float* yh; double* partials;
+  int32_t m; float sigma, a, gamma;
+};
+
+template <int L, bool RES>
+__global__ __launch_bounds__(kBlock) void k_dual32(Dual32Args p) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = t / L;
+  const int lane = threadIdx.x & (L - 1);
+  float acc = 0.0f;
+  double adx = 0.0;
+  if (i < p.m) {
+    const int s = p.rp[i], e = p.rp[i + 1];
+    for (int q = s + lane; q < e; q += L) {
+      const float v = p.val[q];
+      const int c = p.col[q];
+      acc += v * p.xbar[c];
+      if (RES) adx += (double)v * (double)p.dx[c];
+    }
+  }
+  acc = group_sum<L>(acc);
+  if (RES) adx = group_sum<L>(adx);
+  double q[3] = {0.0, 0.0, 0.0};
+  if (i < p.m && lane == 0) {
+    const float yi = p.y[i];
+    const float w = acc - (p.b[i] + yi) / p.sigma;
+    const float yh = yi + p.sigma * (clampv(w, p.lc[i], p.uc[i]) - acc);
+    const float yai = p.ya[i];
+    p.y[i] = p.a * ((1.0f + p.gamma) * yh - p.gamma * yi) + (1.0f - p.a) * yai;
+    if (RES) {
+      p.yh[i] = yh;
+      const double dy = (double)(yi - yh);
+      q[0] = dy * dy;
+      q[1] = dy * adx;
+      const double e = (double)(yh - yai);
+      q[2] = e * e;
+    }
+  }
+  if (RES) block_reduce_store<3>(q, p.partials + (int64_t)blockIdx.x * kRegionStride);
+}
+
+// ============================================================================ elementwise
+__global__ void k_restart_copy(double* x, double* xa, const double* xh, double* y, double* ya,
+                               const double* yh, int32_t n, int32_t m, int32_t to_current) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) {
+    double v = to_current ? x[i] : xh[i];
+    xa[i] = v;
+    x[i] = v;
+  }
+  if (i < m) {
+    double v = to_current ? y[i] : yh[i];
+    ya[i] = v;
+    y[i] = v;
+  }
+}
+
+__global__ void k_warm_start(const double* x0, const double* y0, const double* dr, const double* dc,
+                             double* x, double* xa, double* y, double* ya, int32_t n, int32_t m) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) {
+    double v = x0 ? x0[i] / dc[i] : 0.0;
+    x[i] = v;
+    xa[i] = v;
+  }
+  if (i < m) {
+    double v = y0 ? y0[i] / dr[i] : 0.0;
+    y[i] = v;
+    ya[i] = v;
+  }
+}
+
+__global__ void k_unscale(const double* xh, const double* yh, const double* dr, const double* dc,
+                          double* x, double* y, int32_t n, int32_t m) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (x && i < n) x[i] = dc[i] * xh[i];
+  if (y && i < m) y[i] = dr[i] * yh[i];
+}
+
+__global__ void k_trace(const double* xh, const double* yh, const double* x, const double* y,
+                        double* dst, int32_t n, int32_t m) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) {
+    dst[i] = xh[i];
+    dst[(int64_t)n + m + i] = x[i];
+  }
+  if (i < m) {
+    dst[(int64_t)n + i] = yh[i];
+    dst[2 * (int64_t)n + m + i] = y[i];
+  }
+}
+
+__global__ void k_trace32(const float* xh, const float* yh, const float* x, const float* y,
+                          const double* xc, const double* yc, double P, double D, double* dst,
+                          int32_t n, int32_t m) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) {
+    dst[i] = xc[i] + (double)xh[i] / P;
+    dst[(int64_t)n + m + i] = xc[i] + (double)x[i] / P;
+  }
+  if (i < m) {
+    dst[(int64_t)n + i] = yc[i] + (double)yh[i] / D;
+    dst[2 * (int64_t)n + m + i] = yc[i] + (double)y[i] / D;
+  }
+}
+
+__global__ void k_poison(double* x) { x[0] = __builtin_nan(""); }
+
+// xh <- xc + xh32/P, yh <- yc + yh32/D (the FP64 point of the shifted iterate)
+__global__ void k_combine(const float* xh32, const float* yh32, const double* xc, const double* yc,
+                          double P, double D, double* xh, double* yh, int32_t n, int32_t m) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) xh[i] = xc[i] + (double)xh32[i] / P;
+  if (i < m) yh[i] = yc[i] + (double)yh32[i] / D;
+}
+
+// New centre (xc, yc) <- (xh, yh) and the correction data from FP64 residuals
+// A~ xc (ax) and A~^T yc (aty), both computed at the last check.
+__global__ void k_recentre(const double* xh, const double* yh, const double* ax, const double* aty,
+                           const double* ct, const double* lvt, const double* uvt, const double* lct,
+                           const double* uct, double P, double D, double* xc, double* yc, float* c32,
+                           float* lv32, float* uv32, float* lc32, float* uc32, float* b32, float* x32,
+                           float* xa32, float* y32, float* ya32, int32_t n, int32_t m) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) {
+    const double v = xh[i];
+    xc[i] = v;
+    c32[i] = (float)(D * (ct[i] - aty[i]));
+    lv32[i] = (float)(P * (lvt[i] - v));
+    uv32[i] = (float)(P * (uvt[i] - v));
+    x32[i] = 0.0f;
+    xa32[i] = 0.0f;
+  }
+  if (i < m) {
+    const double v = yh[i];
+    yc[i] = v;
+    lc32[i] = (float)(P * (lct[i] - ax[i]));
+    uc32[i] = (float)(P * (uct[i] - ax[i]));
+    b32[i] = (float)(D * v);
+    y32[i] = 0.0f;
+    ya32[i] = 0.0f;
+  }
+}
+
+// ============================================================================ finalize
+struct Region {
+  const double* p;
+  int64_t nb;
+  int32_t nq;
+  uint32_t max_mask;
+  int8_t q[8];
+};
+struct FinArgs {
+  Region r[4];
+  double* dst;
+};
+
+// One block per region; each quantity summed (or maxed) over blocks in order.
+__global__ void k_finalize(FinArgs a) {
+  const Region R = a.r[blockIdx.x];
+  for (int k = 0; k < R.nq; ++k) {
+    const bool mx = (R.max_mask >> k) & 1u;
+    double s = 0.0;
+    for (int64_t b = threadIdx.x; b < R.nb; b += kBlock) {
+      const double v = R.p[b * kRegionStride + k];
+      s = mx ? (v > s ? v : s) : s + v;
+    }
+    double v[1] = {s};
+    __shared__ double tot[1];
+    block_reduce_store<1>(v, tot, mx ? 1u : 0u);
+    __syncthreads();
+    if (threadIdx.x == 0) a.dst[R.q[k]] = tot[0];
+    __syncthreads();
+  }
+}
+
+// ============================================================================ dispatch
+template <int L>
+struct PrimalL {
+  static hipError_t run(const PrimalArgs& a, bool res, int nb, hipStream_t s) {
+    if (res) hipLaunchKernelGGL((k_primal<L, true>), dim3(nb), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_primal<L, false>), dim3(nb), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+  }
+};
+template <int L>
+struct DualL {
+  static hipError_t run(const DualArgs& a, bool res, int nb, hipStream_t s) {
+    if (res) hipLaunchKernelGGL((k_dual<L, true>), dim3(nb), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_dual<L, false>), dim3(nb), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+  }
+};
+template <int L>
+struct Primal32L {
+  static hipError_t run(const Primal32Args& a, bool res, int nb, hipStream_t s) {
+    if (res) hipLaunchKernelGGL((k_primal32<L, true>), dim3(nb), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_primal32<L, false>), dim3(nb), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+  }
+};
+template <int L>
+struct Dual32L {
+  static hipError_t run(const Dual32Args& a, bool res, int nb, hipStream_t s) {
+    if (res) hipLaunchKernelGGL((k_dual32<L, true>), dim3(nb), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_dual32<L, false>), dim3(nb), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+  }
+};
+template <int L>
+struct KktColsL {
+  static hipError_t run(const KktColArgs& a, bool mixed, int nb, hipStream_t s) {
+    if (mixed) hipLaunchKernelGGL((k_kkt_cols<L, true>), dim3(nb), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_kkt_cols<L, false>), dim3(nb), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+  }
+};
+template <int L>
+struct KktRowsL {
+  static hipError_t run(const KktRowArgs& a, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_kkt_rows<L>), dim3(nb), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+  }
+};
+
+template <template <int> class F, typename... Args>
+hipError_t dispatch_L(int L, Args... args) {
+  switch (L) {
+    case 1: return F<1>::run(args...);
+    case 2: return F<2>::run(args...);
+    case 4: return F<4>::run(args...);
+    case 8: return F<8>::run(args...);
+    case 16: return F<16>::run(args...);
+    case 32: return F<32>::run(args...);
+    default: return F<64>::run(args...);
+  }
+}
+
+Region make_region(const double* p, int64_t nb, std::initializer_list<int> qs, uint32_t max_mask) {
+  Region r{};
+  r.p = p;
+  r.nb = nb;
+  r.nq = (int32_t)qs.size();
+  r.max_mask = max_mask;
+  int k = 0;
+  for (int q : qs) r.q[k++] = (int8_t)q;
+  return r;
+}
+
+}  // namespace
+
+// ============================================================================ launchers
+hipError_t launch_primal(hlp_lp* lp, const StepArgs& s) {
+  if (lp->n == 0) return hipSuccess;
+  PrimalArgs a{lp->cp, lp->row, lp->tval, lp->y, lp->x, lp->xa, lp->ct, lp->lvt, lp->uvt,
+               lp->xbar, lp->xh, lp->dxv, region(lp, R_PRIMAL), lp->n, s.tau, s.a, s.gamma};
+  return dispatch_L<PrimalL>(lp->Lc, a, (bool)s.residual, nblocks((int64_t)lp->n * lp->Lc), lp->stream);
+}
+
+hipError_t launch_dual(hlp_lp* lp, const StepArgs& s) {
+  if (lp->m == 0) return hipSuccess;
+  DualArgs a{lp->rp, lp->col, lp->val, lp->xbar, lp->dxv, lp->xh, lp->y, lp->ya, lp->lct, lp->uct,
+             lp->dr, lp->yh, region(lp, R_DUAL), lp->m, s.sigma, s.a, s.gamma};
+  return dispatch_L<DualL>(lp->Lr, a, (bool)s.residual, nblocks((int64_t)lp->m * lp->Lr), lp->stream);
+}
+
+hipError_t launch_kkt_cols(hlp_lp* lp, int32_t slot, double* r_out) {
+  (void)slot;
+  if (lp->n == 0) return hipSuccess;
+  const bool mixed = lp->precision == HLP_MIXED;
+  KktColArgs a{lp->cp, lp->row, lp->tval, lp->yh, lp->xh, lp->ct, lp->lvt, lp->uvt, lp->dc, r_out,
+               lp->atyc, region(lp, R_KKT), lp->n};
+  return dispatch_L<KktColsL>(lp->Lc, a, mixed, nblocks((int64_t)lp->n * lp->Lc), lp->stream);
+}
+
+hipError_t launch_kkt_rows(hlp_lp* lp, int32_t slot) {
+  (void)slot;
+  if (lp->m == 0) return hipSuccess;
+  KktRowArgs a{lp->rp, lp->col, lp->val, lp->xh, lp->yh, lp->lct, lp->uct, lp->dr, lp->axc,
+               region(lp, R_ROWS), lp->m};
+  return dispatch_L<KktRowsL>(lp->Lr, a, nblocks((int64_t)lp->m * lp->Lr), lp->stream);
+}
+
+// which: bit 0 primal region, bit 1 dual region, bit 2 KKT-cols region,
+// bit 3 KKT-rows region (mixed); bit 4 selects the FP32 layouts.
+hipError_t launch_finalize(hlp_lp* lp, int32_t which, int32_t slot) {
+  FinArgs a{};
+  a.dst = lp->results + (int64_t)slot * NQ;
+  int nr = 0;
+  const bool f32 = (which & 16) != 0;
+  const int64_t nbp = lp->n ? nblocks((int64_t)lp->n * lp->Lc) : 0;
+  const int64_t nbd = lp->m ? nblocks((int64_t)lp->m * lp->Lr) : 0;
+  if (which & 1) a.r[nr++] = make_region(region(lp, R_PRIMAL), nbp, {Q_DX2, Q_XA2}, 0u);
+  if (which & 2) {
+    if (f32) a.r[nr++] = make_region(region(lp, R_DUAL), nbd, {Q_DY2, Q_DYADX, Q_YA2}, 0u);
+    else a.r[nr++] = make_region(region(lp, R_DUAL), nbd, {Q_DY2, Q_DYADX, Q_YA2, Q_RP2, Q_DOBJ_R}, 0u);
+  }
+  if (which & 4) {
+    if (lp->precision == HLP_MIXED)
+      a.r[nr++] = make_region(region(lp, R_KKT), nbp, {Q_RD2, Q_DOBJ_C, Q_POBJ, Q_VD, Q_VX}, 8u | 16u);
+    else a.r[nr++] = make_region(region(lp, R_KKT), nbp, {Q_RD2, Q_DOBJ_C, Q_POBJ}, 0u);
+  }
+  if (which & 8) a.r[nr++] = make_region(region(lp, R_ROWS), nbd, {Q_RP2, Q_DOBJ_R, Q_VP}, 4u);
+  if (nr == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize, dim3(nr), dim3(kBlock), 0, lp->stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_restart_copy(hlp_lp* lp, int32_t to_current) {
+  int64_t N = lp->m > lp->n ? lp->m : lp->n;
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_restart_copy, dim3(nblocks(N)), dim3(kBlock), 0, lp->stream, lp->x, lp->xa, lp->xh,
+                     lp->y, lp->ya, lp->yh, lp->n, lp->m, to_current);
+  return hipGetLastError();
+}
+
+hipError_t launch_warm_start(hlp_lp* lp, const double* x0, const double* y0) {
+  int64_t N = lp->m > lp->n ? lp->m : lp->n;
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_warm_start, dim3(nblocks(N)), dim3(kBlock), 0, lp->stream, x0, y0, lp->dr, lp->dc,
+                     lp->x, lp->xa, lp->y, lp->ya, lp->n, lp->m);
+  return hipGetLastError();
+}
+
+hipError_t launch_unscale(hlp_lp* lp, double* x, double* y) {
+  int64_t N = lp->m > lp->n ? lp->m : lp->n;
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unscale, dim3(nblocks(N)), dim3(kBlock), 0, lp->stream, lp->xh, lp->yh, lp->dr,
+                     lp->dc, x, y, lp->n, lp->m);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace(hlp_lp* lp, double* dst) {
+  int64_t N = lp->m > lp->n ? lp->m : lp->n;
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_trace, dim3(nblocks(N)), dim3(kBlock), 0, lp->stream, lp->xh, lp->yh, lp->x, lp->y,
+                     dst, lp->n, lp->m);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace32(hlp_lp* lp, double* dst, double P, double D) {
+  int64_t N = lp->m > lp->n ? lp->m : lp->n;
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_trace32, dim3(nblocks(N)), dim3(kBlock), 0, lp->stream, lp->xh32, lp->yh32, lp->x32,
+                     lp->y32, lp->xcen, lp->ycen, P, D, dst, lp->n, lp->m);
+  return hipGetLastError();
+}
+
+hipError_t launch_poison(hlp_lp* lp) {
+  if (lp->n == 0) return hipSuccess;
+  if (lp->precision == HLP_MIXED) return hipSuccess;
+  hipLaunchKernelGGL(k_poison, dim3(1), dim3(1), 0, lp->stream, lp->x);
+  return hipGetLastError();
+}
+
+hipError_t launch_primal32(hlp_lp* lp, const StepArgs& s) {
+  if (lp->n == 0) return hipSuccess;
+  Primal32Args a{lp->cp, lp->row, lp->tval32, lp->y32, lp->x32, lp->xa32, lp->c32, lp->lv32, lp->uv32,
+                 lp->xbar32, lp->xh32, lp->dx32, region(lp, R_PRIMAL), lp->n,
+                 (float)s.tau, (float)s.a, (float)s.gamma};
+  return dispatch_L<Primal32L>(lp->Lc, a, (bool)s.residual, nblocks((int64_t)lp->n * lp->Lc), lp->stream);
+}
+
+hipError_t launch_dual32(hlp_lp* lp, const StepArgs& s) {
+  if (lp->m == 0) return hipSuccess;
+  Dual32Args a{lp->rp, lp->col, lp->val32, lp->xbar32, lp->dx32, lp->y32, lp->ya32, lp->lc32, lp->uc32,
+               lp->b32, lp->yh32, region(lp, R_DUAL), lp->m, (float)s.sigma, (float)s.a, (float)s.gamma};
+  return dispatch_L<Dual32L>(lp->Lr, a, (bool)s.residual, nblocks((int64_t)lp->m * lp->Lr), lp->stream);
+}
+
+hipError_t launch_combine(hlp_lp* lp, double P, double D) {
+  int64_t N = lp->m > lp->n ? lp->m : lp->n;
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_combine, dim3(nblocks(N)), dim3(kBlock), 0, lp->stream, lp->xh32, lp->yh32, lp->xcen,
+                     lp->ycen, P, D, lp->xh, lp->yh, lp->n, lp->m);
+  return hipGetLastError();
+}
+
+hipError_t launch_recentre(hlp_lp* lp, double P, double D) {
+  int64_t N = lp->m > lp->n ? lp->m : lp->n;
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_recentre, dim3(nblocks(N)), dim3(kBlock), 0, lp->stream, lp->xh, lp->yh, lp->axc,
+                     lp->atyc, lp->ct, lp->lvt, lp->uvt, lp->lct, lp->uct, P, D, lp->xcen, lp->ycen, lp->c32,
+                     lp->lv32, lp->uv32, lp->lc32, lp->uc32, lp->b32, lp->x32, lp->xa32, lp->y32, lp->ya32,
+                     lp->n, lp->m);
+  return hipGetLastError();
+}
+
+}  // namespace hlp

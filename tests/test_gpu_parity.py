@@ -1,0 +1,216 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle.
+
+Bars: setup steps (transpose indices, row/column pointers) bit-exact; scaling
+diagonals and eta within 1e-12 relative; the iterate trajectory of the first
+100 iterations within 1e-10 relative per iteration (only the summation order
+differs); the same restart iterations, primal weights and iteration count;
+the returned point meets the tolerance by the oracle's own KKT routine.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import lpgen
+import oracle
+from oracle.pdhg import Params, power_norm, rescale
+from tests._gpu import announce, np_out, problem, rel
+
+pytestmark = pytest.mark.gpu
+
+TRAJ_TOL = 1e-10
+
+
+def _trajectory_case(lp, T=100, **kw):
+    prob = problem(lp)
+    dr, dc, eta, pit = prob.scaling()
+    out = prob.solve(trace_iters=T, **kw)
+    ref = oracle.solve(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, Params(eta_override=eta, trace_iters=T, **kw))
+    tr = {k: v.cpu().numpy() for k, v in out["trace"].items()}
+    Tn = min(T, out["info"]["iters"], ref.iters)
+    worst = 0.0
+    for key in ("xh", "yh", "x", "y"):
+        for t in range(Tn):
+            e = rel(tr[key][t], ref.trace[key][t])
+            worst = max(worst, e)
+            assert e <= TRAJ_TOL, (key, t, e)
+    prob.close()
+    return out, ref, worst
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_trajectory_c1(seed):
+    lp = lpgen.config("c1", seed=seed)
+    announce(f"trajectory c1 seed={seed} m={lp.m} n={lp.n} nnz={lp.nnz}")
+    out, ref, worst = _trajectory_case(lp, T=100, tol=1e-8)
+    info = out["info"]
+    assert info["status"] == oracle.pdhg.OPTIMAL == ref.status
+    assert info["iters"] == ref.iters and info["restarts"] == ref.restarts
+    assert info["omega"] == pytest.approx(ref.omega, rel=1e-9)
+    k = oracle.kkt(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, out["x"].cpu().numpy(), out["y"].cpu().numpy())
+    assert k["rel_kkt"] <= 1e-8 * (1 + 1e-6)
+    assert abs(k["rel_kkt"] - info["rel_kkt"]) <= 1e-6 * k["rel_kkt"] + 1e-15
+    assert abs(k["pobj"] - info["pobj"]) <= 1e-12 * (1 + abs(k["pobj"]))
+    print(f"worst trajectory error {worst:.2e}")
+
+
+def test_trajectory_all_bound_types_eval_every_iteration():
+    """Every bound pattern of the sets Y and R; checks at every iteration (the
+    paper's literal reading), so restarts fire inside the traced window."""
+    lp = lpgen.gen_mixed(300, 400, rowlen=4, seed=3)
+    announce("trajectory gen_mixed 300x400 eval_freq=1")
+    out, ref, _ = _trajectory_case(lp, T=100, tol=1e-9, eval_freq=1)
+    assert out["info"]["restarts"] == ref.restarts >= 1
+    assert out["info"]["iters"] == ref.iters
+
+
+def test_trajectory_c2_first_100_iterations():
+    lp = lpgen.config("c2", seed=1)
+    announce(f"trajectory c2 m={lp.m} n={lp.n} nnz={lp.nnz}")
+    out, ref, worst = _trajectory_case(lp, T=100, max_iter=100)
+    assert out["info"]["restarts"] == ref.restarts
+    assert out["info"]["omega"] == pytest.approx(ref.omega, rel=1e-9)
+
+
+def test_transpose_and_scaling_match_oracle():
+    lp = lpgen.config("c1", seed=4)
+    announce("transpose + scaling c1 seed=4")
+    prob = problem(lp)
+    cp, ri, tv = (t.cpu().numpy() for t in prob.transpose())
+    dr, dc, eta, pit = prob.scaling()
+    At, dr0, dc0 = rescale(lp.A, 10, 1)
+    T = At.T.tocsr()
+    T.sort_indices()
+    np.testing.assert_array_equal(cp, T.indptr)
+    np.testing.assert_array_equal(ri, T.indices)
+    np.testing.assert_allclose(tv, T.data, rtol=1e-13)
+    np.testing.assert_allclose(dr.cpu().numpy(), dr0, rtol=1e-13)
+    np.testing.assert_allclose(dc.cpu().numpy(), dc0, rtol=1e-13)
+    nrm, it = power_norm(At, 5000, 1e-8)
+    assert eta == pytest.approx(0.998 / nrm, rel=1e-12)
+    assert pit == it
+    prob.close()
+
+
+def test_transpose_skewed_rows_and_empty_columns():
+    """Zipf row lengths (a few long rows, many 1-nnz rows) and empty columns."""
+    lp = lpgen.gen(3000, 9000, zipf_alpha=1.5, cap=2500, eq_frac=0.3, free_frac=0.2, values="logu", seed=5)
+    announce(f"transpose skewed m={lp.m} n={lp.n} nnz={lp.nnz} max_row={lp.meta['max_row']}")
+    prob = problem(lp, ruiz_iters=0, pock_chambolle=0)
+    cp, ri, tv = (t.cpu().numpy() for t in prob.transpose())
+    T = lp.A.T.tocsr()
+    T.sort_indices()
+    np.testing.assert_array_equal(cp, T.indptr)
+    np.testing.assert_array_equal(ri, T.indices)
+    np.testing.assert_array_equal(tv, T.data)       # no scaling: values copied exactly
+    prob.close()
+
+
+def test_power_iteration_matches_oracle_on_skewed():
+    lp = lpgen.gen(2000, 5000, zipf_alpha=1.7, cap=1500, eq_frac=0.3, free_frac=0.2, values="logu", seed=2)
+    announce(f"power iteration skewed nnz={lp.nnz}")
+    prob = problem(lp)
+    _, _, eta, pit = prob.scaling()
+    At, _, _ = rescale(lp.A, 10, 1)
+    nrm, it = power_norm(At, 5000, 1e-8)
+    assert eta == pytest.approx(0.998 / nrm, rel=1e-9)
+    assert abs(pit - it) <= 1
+    prob.close()
+
+
+def test_solve_skewed_rows_reaches_tolerance():
+    lp = lpgen.gen(2000, 5000, zipf_alpha=1.7, cap=1500, eq_frac=0.3, free_frac=0.2, values="logu", seed=2)
+    announce("solve skewed to 1e-6")
+    prob = problem(lp)
+    out = np_out(prob.solve(tol=1e-6, max_iter=200000))
+    k = oracle.kkt(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, out["x"], out["y"])
+    assert out["info"]["status"] == oracle.pdhg.OPTIMAL
+    assert k["rel_kkt"] <= 1e-6 * (1 + 1e-6)
+    prob.close()
+
+
+def test_zero_matrix_and_empty_rows():
+    """A = 0 (no nonzeros): eta = 1 and the box closed form."""
+    rng = np.random.default_rng(3)
+    m, n = 5, 40
+    A = sp.csr_matrix((m, n))
+    c = rng.standard_normal(n)
+    lv = -rng.random(n); uv = rng.random(n)
+    lp = lpgen.LP(A, c, -np.ones(m), np.ones(m), lv, uv)
+    announce("zero matrix")
+    prob = problem(lp)
+    _, _, eta, _ = prob.scaling()
+    assert eta == 1.0
+    out = np_out(prob.solve(tol=1e-12, eval_freq=4))
+    assert out["info"]["status"] == oracle.pdhg.OPTIMAL
+    np.testing.assert_allclose(out["x"], np.where(c > 0, lv, uv), atol=1e-10)
+    prob.close()
+
+
+def test_ragged_tiny_and_single_row():
+    lp = lpgen.gen_mixed(7, 9, rowlen=3, seed=8, box_only=True)
+    announce("tiny 7x9")
+    out, ref, _ = _trajectory_case(lp, T=50, tol=1e-10, eval_freq=8)
+    assert out["info"]["iters"] == ref.iters
+
+
+def test_limits_and_numerical_status():
+    from paper_2507_14051_amd import ITER_LIMIT, NUMERICAL, TIME_LIMIT
+    lp = lpgen.config("c1", seed=1)
+    announce("limits c1")
+    prob = problem(lp)
+    assert prob.solve(max_iter=1)["info"]["status"] == ITER_LIMIT
+    out = prob.solve(time_limit_s=0.0)
+    assert out["info"]["status"] == TIME_LIMIT and out["info"]["iters"] == 64
+    out = prob.solve(debug_poison_iter=10)
+    assert out["info"]["status"] == NUMERICAL and out["info"]["iters"] == 64
+    prob.close()
+
+
+def test_repeatable_bitwise():
+    lp = lpgen.config("c1", seed=2)
+    announce("determinism c1")
+    prob = problem(lp)
+    a = np_out(prob.solve(tol=1e-8))
+    b = np_out(prob.solve(tol=1e-8))
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["y"], b["y"])
+    assert a["info"]["iters"] == b["info"]["iters"]
+    prob.close()
+
+
+@pytest.mark.parametrize("bad", ["nan_c", "l_gt_u", "col_range", "unsorted", "plus_inf_lower",
+                                 "rowptr_decreasing", "nan_value"])
+def test_validation_errors(bad):
+    from paper_2507_14051_amd import HlpError, Problem
+    lp = lpgen.gen_mixed(6, 8, rowlen=3, seed=1)
+    A, c, lc, uc, lv, uv = lp.A.copy(), lp.c.copy(), lp.lc.copy(), lp.uc.copy(), lp.lv.copy(), lp.uv.copy()
+    rp, ci, va = A.indptr.astype(np.int64).copy(), A.indices.astype(np.int32).copy(), A.data.copy()
+    if bad == "nan_c":
+        c[2] = np.nan
+    elif bad == "l_gt_u":
+        lv[0], uv[0] = 1.0, 0.0
+    elif bad == "col_range":
+        ci[0] = 8
+    elif bad == "unsorted":
+        ci[0], ci[1] = ci[1], ci[0]
+    elif bad == "plus_inf_lower":
+        lc[1] = np.inf
+    elif bad == "rowptr_decreasing":
+        rp[2], rp[3] = rp[3], rp[2]
+    elif bad == "nan_value":
+        va[4] = np.nan
+    announce(f"validation {bad}")
+    with pytest.raises(HlpError) as e:
+        Problem(((rp, ci, va), A.shape), c, lc, uc, lv, uv, device="cuda:0")
+    assert e.value.code == -1
+
+
+def test_warm_start_at_solution_stops_at_first_check():
+    lp = lpgen.config("c1", seed=1)
+    announce("warm start c1")
+    prob = problem(lp)
+    a = np_out(prob.solve(tol=1e-9))
+    b = prob.solve(tol=1e-6, x0=a["x"], y0=a["y"])
+    assert b["info"]["status"] == oracle.pdhg.OPTIMAL and b["info"]["iters"] == 64
+    prob.close()
