@@ -85,10 +85,10 @@ def _columns_var(rng, n, lengths):
         rows = np.nonzero(lengths == L)[0]
         if L == 0:
             continue
-        if L * 4 >= n:  # dense relative to n: permutation prefix, exact w/o replacement
+        if L * L > n:  # repeats likely: draw each row directly without replacement
             block = np.empty((rows.size, L), dtype=np.int64)
             for i in range(rows.size):
-                block[i] = np.sort(rng.permutation(n)[:L])
+                block[i] = np.sort(rng.choice(n, size=L, replace=False))
         else:
             block = _columns_fixed(rng, rows.size, n, int(L))
         starts = indptr[rows]

@@ -139,8 +139,10 @@ hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s
 // Iteration (kernels_iter.hip).
 struct StepArgs {
   double tau, sigma, a, gamma;
-  int32_t residual;   // compute the check quantities and write xhat / yhat
-  int32_t slot;       // result slot for the finalize
+  int32_t residual;          // compute the check quantities and write xhat / yhat
+  int32_t slot;              // result slot for the finalize
+  uint8_t* mask_x = nullptr; // if set (FP64 only): write xhat and the clamp codes of v
+  uint8_t* mask_y = nullptr; // if set (FP64 only): write yhat and the clamp codes of w
 };
 hipError_t launch_primal(hlp_lp* lp, const StepArgs& s);
 hipError_t launch_dual(hlp_lp* lp, const StepArgs& s);
@@ -161,21 +163,23 @@ hipError_t launch_recentre(hlp_lp* lp, double P, double D);  // rebuild the corr
 hipError_t launch_zero_mixed(hlp_lp* lp);
 hipError_t launch_trace32(hlp_lp* lp, double* dst, double P, double D);
 
-// Adjoint (kernels_adjoint.hip).
-struct AdjStep {
-  double tau, sigma, a, gamma;
-  int32_t mode;  // 0: Halpern step; 1: restart after the step; 2: last iteration (output)
+// Adjoint (kernels_adjoint.hip).  Reverse mode of one iteration; mode of the
+// iteration: 0 Halpern update after it, 1 restart after it, 2 the last one.
+struct AdjVecs {
+  double *gxn, *gxa, *gct, *glv, *guv, *u;   // n
+  double *gyn, *gya, *glc, *guc, *gw, *py;   // m
 };
-hipError_t launch_fwd_masks(hlp_lp* lp, const StepArgs& s, uint8_t* mx, uint8_t* my);
-hipError_t launch_bwd_init(hlp_lp* lp, const double* gx, const double* gy, double* adj, const AdjStep& st,
-                           const uint8_t* my);
-hipError_t launch_bwd_cols(hlp_lp* lp, double* adj, const AdjStep& st, const uint8_t* mx);
-hipError_t launch_bwd_rows(hlp_lp* lp, double* adj, const AdjStep& st, const AdjStep& prev,
-                           const uint8_t* my_prev, int32_t has_prev);
-hipError_t launch_bwd_out(hlp_lp* lp, const double* adj, double* gc, double* glc, double* guc,
-                          double* glv, double* guv);
+struct AdjIter {
+  double tau, sigma, a, gamma;
+  int32_t mode;
+};
+hipError_t launch_bwd_prep(hlp_lp* lp, const AdjVecs& v, const AdjIter& it, const uint8_t* my, const double* Gy);
+hipError_t launch_bwd_cols(hlp_lp* lp, const AdjVecs& v, const AdjIter& it, const uint8_t* mx, const double* Gx);
+hipError_t launch_bwd_rows(hlp_lp* lp, const AdjVecs& v, int32_t do_prev, const AdjIter& prev,
+                           const uint8_t* my_prev, const double* Gy);
+hipError_t launch_bwd_out(hlp_lp* lp, const AdjVecs& v, double* gc, double* glc, double* guc, double* glv,
+                          double* guv);
+hipError_t launch_zero_adj(hlp_lp* lp, const AdjVecs& v);
 
-// Profiling helpers
-hipError_t launch_copy_state(hlp_lp* lp, double* dst, const double* src, int64_t n);
 
 }  // namespace hlp

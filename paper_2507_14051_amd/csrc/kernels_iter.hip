@@ -32,12 +32,15 @@ enum { R_PRIMAL = 0, R_DUAL = 1, R_KKT = 2, R_ROWS = 3 };
 struct PrimalArgs {
   const int32_t* cp; const int32_t* row; const double* tval;
   const double* y; double* x; const double* xa; const double* ct; const double* lv; const double* uv;
-  double* xbar; double* xh; double* dx; double* partials;
+  double* xbar; double* xh; double* dx; double* partials; uint8_t* mask;
   int32_t n; double tau, a, gamma;
 };
 
-template <int L, bool RES>
+// MODE 0: plain step; 1: also xhat, x - xhat and the check partials;
+// 2: also xhat and the clamp code of v (for the reverse mode).
+template <int L, int MODE>
 __global__ __launch_bounds__(kBlock) void k_primal(PrimalArgs p) {
+  constexpr bool RES = MODE == 1;
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t j = t / L;
   const int lane = threadIdx.x & (L - 1);
@@ -58,6 +61,10 @@ __global__ __launch_bounds__(kBlock) void k_primal(PrimalArgs p) {
     p.xbar[j] = 2.0 * xh - xj;
     const double xaj = p.xa[j];
     p.x[j] = p.a * ((1.0 + p.gamma) * xh - p.gamma * xj) + (1.0 - p.a) * xaj;
+    if (MODE == 2) {
+      p.xh[j] = xh;
+      p.mask[j] = clamp_code(v, p.lv[j], p.uv[j]);
+    }
     if (RES) {
       p.xh[j] = xh;
       const double d = xj - xh;
@@ -77,12 +84,14 @@ struct DualArgs {
   const int32_t* rp; const int32_t* col; const double* val;
   const double* xbar; const double* dx; const double* xh;
   double* y; const double* ya; const double* lc; const double* uc; const double* dr;
-  double* yh; double* partials;
+  double* yh; double* partials; uint8_t* mask;
   int32_t m; double sigma, a, gamma;
 };
 
-template <int L, bool RES>
+// MODE as for k_primal (the code is that of w against the row bounds).
+template <int L, int MODE>
 __global__ __launch_bounds__(kBlock) void k_dual(DualArgs p) {
+  constexpr bool RES = MODE == 1;
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i = t / L;
   const int lane = threadIdx.x & (L - 1);
@@ -115,6 +124,10 @@ __global__ __launch_bounds__(kBlock) void k_dual(DualArgs p) {
     const double yh = p.sigma * (clampv(w, lo, hi) - w);
     const double yai = p.ya[i];
     p.y[i] = p.a * ((1.0 + p.gamma) * yh - p.gamma * yi) + (1.0 - p.a) * yai;
+    if (MODE == 2) {
+      p.yh[i] = yh;
+      p.mask[i] = clamp_code(w, lo, hi);
+    }
     if (RES) {
       p.yh[i] = yh;
       const double dy = yi - yh;
@@ -442,17 +455,19 @@ __global__ void k_finalize(FinArgs a) {
 // ============================================================================ dispatch
 template <int L>
 struct PrimalL {
-  static hipError_t run(const PrimalArgs& a, bool res, int nb, hipStream_t s) {
-    if (res) hipLaunchKernelGGL((k_primal<L, true>), dim3(nb), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_primal<L, false>), dim3(nb), dim3(kBlock), 0, s, a);
+  static hipError_t run(const PrimalArgs& a, int mode, int nb, hipStream_t s) {
+    if (mode == 1) hipLaunchKernelGGL((k_primal<L, 1>), dim3(nb), dim3(kBlock), 0, s, a);
+    else if (mode == 2) hipLaunchKernelGGL((k_primal<L, 2>), dim3(nb), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_primal<L, 0>), dim3(nb), dim3(kBlock), 0, s, a);
     return hipGetLastError();
   }
 };
 template <int L>
 struct DualL {
-  static hipError_t run(const DualArgs& a, bool res, int nb, hipStream_t s) {
-    if (res) hipLaunchKernelGGL((k_dual<L, true>), dim3(nb), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_dual<L, false>), dim3(nb), dim3(kBlock), 0, s, a);
+  static hipError_t run(const DualArgs& a, int mode, int nb, hipStream_t s) {
+    if (mode == 1) hipLaunchKernelGGL((k_dual<L, 1>), dim3(nb), dim3(kBlock), 0, s, a);
+    else if (mode == 2) hipLaunchKernelGGL((k_dual<L, 2>), dim3(nb), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_dual<L, 0>), dim3(nb), dim3(kBlock), 0, s, a);
     return hipGetLastError();
   }
 };
@@ -518,15 +533,17 @@ Region make_region(const double* p, int64_t nb, std::initializer_list<int> qs, u
 hipError_t launch_primal(hlp_lp* lp, const StepArgs& s) {
   if (lp->n == 0) return hipSuccess;
   PrimalArgs a{lp->cp, lp->row, lp->tval, lp->y, lp->x, lp->xa, lp->ct, lp->lvt, lp->uvt,
-               lp->xbar, lp->xh, lp->dxv, region(lp, R_PRIMAL), lp->n, s.tau, s.a, s.gamma};
-  return dispatch_L<PrimalL>(lp->Lc, a, (bool)s.residual, nblocks((int64_t)lp->n * lp->Lc), lp->stream);
+               lp->xbar, lp->xh, lp->dxv, region(lp, R_PRIMAL), s.mask_x, lp->n, s.tau, s.a, s.gamma};
+  const int mode = s.mask_x ? 2 : (s.residual ? 1 : 0);
+  return dispatch_L<PrimalL>(lp->Lc, a, mode, nblocks((int64_t)lp->n * lp->Lc), lp->stream);
 }
 
 hipError_t launch_dual(hlp_lp* lp, const StepArgs& s) {
   if (lp->m == 0) return hipSuccess;
   DualArgs a{lp->rp, lp->col, lp->val, lp->xbar, lp->dxv, lp->xh, lp->y, lp->ya, lp->lct, lp->uct,
-             lp->dr, lp->yh, region(lp, R_DUAL), lp->m, s.sigma, s.a, s.gamma};
-  return dispatch_L<DualL>(lp->Lr, a, (bool)s.residual, nblocks((int64_t)lp->m * lp->Lr), lp->stream);
+             lp->dr, lp->yh, region(lp, R_DUAL), s.mask_y, lp->m, s.sigma, s.a, s.gamma};
+  const int mode = s.mask_y ? 2 : (s.residual ? 1 : 0);
+  return dispatch_L<DualL>(lp->Lr, a, mode, nblocks((int64_t)lp->m * lp->Lr), lp->stream);
 }
 
 hipError_t launch_kkt_cols(hlp_lp* lp, int32_t slot, double* r_out) {
