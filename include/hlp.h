@@ -93,6 +93,9 @@ typedef struct {
   int32_t trace_iters;     /* > 0: record the first trace_iters iterates (see hlp_solve); 0 */
   int32_t debug_poison_iter; /* > 0: write NaN into x after that iteration (tests the
                                 HLP_NUMERICAL path from the host); 0 */
+  int32_t graphs;          /* 1: replay each run of eval_freq iterations (and its check)
+                              from a captured HIP graph; 0: launch every kernel; 1.
+                              Results are bitwise identical either way. */
 } hlp_params;
 
 /* Outcome of a solve.  Objectives and relative errors refer to the original

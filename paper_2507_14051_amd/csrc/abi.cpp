@@ -116,8 +116,13 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
   L->ycen = c.take<double>(m);
   L->axc = c.take<double>(m);
   L->atyc = c.take<double>(n);
-  // reductions: 4 regions of partial_blocks x 8 doubles (lanes per row <= 64)
-  L->partial_blocks = (N * 64 + 255) / 256 + 1;
+  // row blocks and the step scalars
+  L->rbA = c.take<int32_t>((int64_t)m + 2);
+  L->rbT = c.take<int32_t>((int64_t)n + 2);
+  L->rbtmp = c.take<int32_t>(2 * (N + 1));
+  L->step = c.take<StepDev>(1);
+  // reductions: 4 regions of partial_blocks x 8 doubles (at most one block per row)
+  L->partial_blocks = N + 2;
   L->partials = c.take<double>(4 * L->partial_blocks * 8);
   L->results = c.take<double>(NSLOT * NQ);
   L->pstate = c.take<PowerState>(1);
@@ -131,7 +136,7 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
   const int64_t nbr = (nnz + 4095) / 4096;
   L->hist_len = 256 * std::max<int64_t>(nbr, 1);
   L->hist = c.take<int32_t>(L->hist_len);
-  L->scan_tmp_len = std::max<int64_t>(L->hist_len, (int64_t)n + 1) / 1024 + 2;
+  L->scan_tmp_len = std::max<int64_t>(L->hist_len, N + 1) / 1024 + 2;
   L->scan_tmp = c.take<int32_t>(L->scan_tmp_len);
   // power iteration vectors alias iteration buffers (setup only)
   L->pv = L->rbuf;
@@ -176,6 +181,7 @@ hlp_err hlp_params_default(hlp_params* p) {
   p->pid_min_norm = 1e-10;
   p->trace_iters = 0;
   p->debug_poison_iter = 0;
+  p->graphs = 1;
   return HLP_OK;
 }
 
@@ -309,6 +315,19 @@ hlp_err hlp_lp_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr,
   lp->Lr = lanes_for(m ? (double)nnz / m : 1.0);
   lp->Lc = lanes_for(n ? (double)nnz / n : 1.0);
   if (hipError_t e = launch_transpose(lp); e != hipSuccess) return fail(hip_fail(e, "transpose"));
+  // row blocks of A~ and A~^T for the hot SpMVs
+  if (hipError_t e = launch_build_row_blocks(lp, lp->rp, m, lp->rbA, lp->flags + 1); e != hipSuccess)
+    return fail(hip_fail(e, "row blocks"));
+  if (hipError_t e = launch_build_row_blocks(lp, lp->cp, n, lp->rbT, lp->flags + 2); e != hipSuccess)
+    return fail(hip_fail(e, "row blocks"));
+  {
+    int32_t cnt[3] = {0, 0, 0};
+    if (hipError_t e = hipMemcpyAsync(cnt, lp->flags, sizeof(cnt), hipMemcpyDeviceToHost, lp->stream); e != hipSuccess)
+      return fail(hip_fail(e, "row block count"));
+    if (hipError_t e = hipStreamSynchronize(lp->stream); e != hipSuccess) return fail(hip_fail(e, "sync"));
+    lp->nbA = m ? cnt[1] : 0;
+    lp->nbT = n ? cnt[2] : 0;
+  }
   // 3. rescaling of A, then the vectors
   if (hipError_t e = launch_rescale(lp, p->ruiz_iters, p->pock_chambolle); e != hipSuccess)
     return fail(hip_fail(e, "rescale"));
@@ -379,6 +398,12 @@ hlp_err hlp_lp_transpose(const hlp_lp* lp, int32_t* col_ptr, int32_t* row_idx, d
   return HLP_OK;
 }
 
-void hlp_lp_destroy(hlp_lp* lp) { delete lp; }
+void hlp_lp_destroy(hlp_lp* lp) {
+  if (!lp) return;
+  for (void*& g : lp->graph_exec)
+    if (g) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(g));
+  if (lp->capture_stream) (void)hipStreamDestroy(lp->capture_stream);
+  delete lp;
+}
 
 }  // extern "C"

@@ -79,6 +79,25 @@ hlp_err state_copy(hlp_lp* lp, double* dst, bool save) {
   return HLP_OK;
 }
 
+// Sets the device step scalars only when a new epoch or primal weight begins:
+// within an epoch the Halpern index grows by one per iteration, so each launch
+// just carries its offset j from the epoch's first iteration.
+struct StepTracker {
+  double eta;
+  int64_t base_t = -1, base_k = 0;
+  double base_om = 0.0;
+  hlp_err at(hlp_lp* lp, int64_t t, double om, int64_t k, double gamma) {
+    if (base_t < 0 || om != base_om || k - base_k != t - base_t) {
+      HLP_HIP(launch_set_step(lp, eta / om, eta * om, gamma, k));
+      base_t = t;
+      base_k = k;
+      base_om = om;
+    }
+    return HLP_OK;
+  }
+  int32_t j(int64_t t) const { return (int32_t)(t - base_t); }
+};
+
 double fixed_point_residual(const double* R, double eta, double omega) {
   double q = (omega / eta) * R[Q_DX2] + 2.0 * R[Q_DYADX] + R[Q_DY2] / (eta * omega);
   return std::sqrt(std::max(q, 0.0));
@@ -142,6 +161,7 @@ hlp_err hlp_unrolled_forward(hlp_lp* lp, const hlp_params* pp, int32_t K, int32_
     }
   }
   const double eta = lp->eta;
+  StepTracker steps{eta};
   HLP_HIP(launch_warm_start(lp, x0, y0));
   double om = p.omega0;
   int64_t k = 0;
@@ -165,7 +185,10 @@ hlp_err hlp_unrolled_forward(hlp_lp* lp, const hlp_params* pp, int32_t K, int32_
     const bool need_r = !replay && (k == 0 || check);
     const bool last = t == K - 1;
     const bool res = need_r || last || (replay && rst[t]);
-    StepArgs s{eta / om, eta * om, (double)(k + 1) / (double)(k + 2), p.gamma, res ? 1 : 0, 0};
+    HLP_TRY(steps.at(lp, t, om, k, p.gamma));
+    StepArgs s;
+    s.j = steps.j(t);
+    s.residual = res ? 1 : 0;
     HLP_HIP(launch_primal(lp, s));
     HLP_HIP(launch_dual(lp, s));
     if (need_r) {
@@ -258,6 +281,7 @@ hlp_err hlp_unrolled_backward(hlp_lp* lp, const void* tape, size_t tape_bytes, c
   HLP_HIP(hipMemcpyAsync(rst.data(), base + L.rst, (size_t)K, hipMemcpyDeviceToHost, lp->stream));
   HLP_HIP(hipStreamSynchronize(lp->stream));
   const double eta = h.eta, gamma = h.gamma;
+  StepTracker steps{eta};
   const AdjVecs v = adj_vecs(base, L, n, m);
   HLP_HIP(launch_zero_adj(lp, v));
   uint8_t* masks = reinterpret_cast<uint8_t*>(base + L.masks);
@@ -272,10 +296,13 @@ hlp_err hlp_unrolled_backward(hlp_lp* lp, const void* tape, size_t tape_bytes, c
   for (int32_t seg = L.nseg - 1; seg >= 0; --seg) {
     const int32_t t0 = seg * ckpt, t1 = std::min(K, t0 + ckpt);
     // recompute the segment's clamp codes from its checkpoint
+    steps.base_t = -1;
     HLP_TRY(state_copy(lp, ck + (size_t)seg * cstride, false));
     for (int32_t t = t0; t < t1; ++t) {
       const double om = omega[t];
-      StepArgs s{eta / om, eta * om, (double)(kidx[t] + 1) / (double)(kidx[t] + 2), gamma, 0, 0};
+      HLP_TRY(steps.at(lp, t, om, kidx[t], gamma));
+      StepArgs s;
+      s.j = steps.j(t);
       s.mask_x = masks + (size_t)(t - t0) * mstride;
       s.mask_y = s.mask_x + n;
       HLP_HIP(launch_primal(lp, s));

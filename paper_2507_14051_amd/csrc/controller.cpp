@@ -3,6 +3,12 @@
 // FP64 or in FP32 with iterative refinement.  All vector work runs in the HIP
 // kernels; the host only keeps the scalar state (omega, PID memory, k, T,
 // r0, r_prev) and reads ~13 reduced FP64 scalars once per check.
+//
+// The iterations between two checks form a "run": the step scalars are set
+// once on the device, then the run's launches (two half-steps per iteration,
+// residual variants at the first iteration of an epoch and at the check, the
+// check's KKT kernel and the finalize kernels) are issued either directly or
+// by replaying a HIP graph captured once per handle and run shape.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -96,131 +102,139 @@ hlp_err check_params(const hlp_params* p) {
   return HLP_OK;
 }
 
-hlp_err read_results(hlp_lp* lp, double* R) {
-  HLP_HIP(hipMemcpyAsync(R, lp->results, sizeof(double) * NSLOT * NQ, hipMemcpyDeviceToHost, lp->stream));
-  HLP_HIP(hipStreamSynchronize(lp->stream));
-  return HLP_OK;
-}
-
-#define HLP_K(call)                                  \
-  do {                                               \
-    hipError_t e_ = (call);                          \
+#define HLP_K(call)                                   \
+  do {                                                \
+    hipError_t e_ = (call);                           \
     if (e_ != hipSuccess) return hip_fail(e_, #call); \
   } while (0)
 
-// ------------------------------------------------------------------ the FP64 loop
-hlp_err solve_fp64(hlp_lp* lp, const hlp_params& p, const double* x0, const double* y0, double* rout,
-                   double* trace, Ctl& c, Kkt& kk, int32_t& status) {
-  const double eta = lp->eta;
-  const int64_t tstride = 2 * (int64_t)lp->n + 2 * (int64_t)lp->m;
-  HLP_K(launch_warm_start(lp, x0, y0));
-  c.omega = p.omega0;
-  bool r0_pending = false;
-  double R[NSLOT * NQ];
-  const double t_start = now_s();
-  while (true) {
-    const double tau = eta / c.omega, sigma = eta * c.omega;
-    const bool check = ((c.t + 1) % p.eval_freq == 0) || (c.t + 1 == p.max_iter);
-    const bool need_r = (c.k == 0) || check;
-    const bool traced = trace && c.t < p.trace_iters;
-    StepArgs s{tau, sigma, (double)(c.k + 1) / (double)(c.k + 2), p.gamma, (need_r || traced) ? 1 : 0, 0};
-    HLP_K(launch_primal(lp, s));
-    HLP_K(launch_dual(lp, s));
-    if (need_r) {
-      HLP_K(launch_finalize(lp, 1 | 2, check ? SLOT_CHECK : SLOT_R0));
-      if (!check) r0_pending = true;
-    }
-    if (traced) HLP_K(launch_trace(lp, trace + c.t * tstride));
-    const bool epoch_start = c.k == 0;
-    ++c.k;
-    ++c.t;
-    if (p.debug_poison_iter > 0 && c.t == p.debug_poison_iter) HLP_K(launch_poison(lp));
-    if (!check) continue;
-    HLP_K(launch_kkt_cols(lp, SLOT_CHECK, rout));
-    HLP_K(launch_finalize(lp, 4, SLOT_CHECK));
-    HLP_TRY(read_results(lp, R));
-    ++c.checks;
-    const double* RC = R + SLOT_CHECK * NQ;
-    const double r = fixed_point_residual(RC, eta, c.omega);
-    if (epoch_start) {
-      c.r0 = r;
-    } else if (r0_pending) {
-      c.r0 = fixed_point_residual(R + SLOT_R0 * NQ, eta, c.omega);
-    }
-    r0_pending = false;
-    kk = kkt_from(RC, lp);
-    status = -1;
-    if (!kk.finite || !std::isfinite(r)) status = HLP_NUMERICAL;
-    else if (kk.rel <= p.tol) status = HLP_OPTIMAL;
-    else if (c.t >= p.max_iter) status = HLP_ITER_LIMIT;
-    else if (now_s() - t_start >= p.time_limit_s) status = HLP_TIME_LIMIT;
-    if (status >= 0) return HLP_OK;
-    if (restart_test(r, c.r0, c.r_prev, c.k, c.t, p)) {
-      ++c.restarts;
-      c.omega = pid_update(c.omega, std::sqrt(RC[Q_XA2]), std::sqrt(RC[Q_YA2]), c, p);
-      HLP_K(launch_restart_copy(lp, p.restart_to_current));
-      c.k = 0;
-      c.r_prev = kInf;
+// One run of `len` iterations ending at a check.  first_res: the first
+// iteration starts an epoch (its residual goes to the R0 slot unless it is
+// also the check).  trace_at(j) / poison_at(j): per-iteration extras (direct
+// launches only).
+struct RunShape {
+  int32_t len;
+  bool first_res;
+  bool mixed;
+};
+
+hlp_err issue_run(hlp_lp* lp, const RunShape& rs, double* trace_base, int64_t trace_first, int64_t trace_n,
+                  int64_t trace_stride, int32_t poison_j) {
+  for (int32_t j = 0; j < rs.len; ++j) {
+    const bool first = j == 0 && rs.first_res;
+    const bool last = j == rs.len - 1;
+    const int64_t tj = trace_first + j;
+    const bool traced = trace_base && tj >= 0 && tj < trace_n;
+    StepArgs s;
+    s.j = j;
+    s.residual = (first || last || traced) ? 1 : 0;
+    if (rs.mixed) {
+      HLP_K(launch_primal32(lp, s));
+      HLP_K(launch_dual32(lp, s));
     } else {
-      c.r_prev = r;
+      HLP_K(launch_primal(lp, s));
+      HLP_K(launch_dual(lp, s));
     }
+    const int f32 = rs.mixed ? 16 : 0;
+    if (first && !last) HLP_K(launch_finalize(lp, 1 | 2 | f32, SLOT_R0));
+    if (last) HLP_K(launch_finalize(lp, 1 | 2 | f32, SLOT_CHECK));
+    if (traced) {
+      if (rs.mixed) HLP_K(launch_trace32(lp, trace_base + tj * trace_stride));
+      else HLP_K(launch_trace(lp, trace_base + tj * trace_stride));
+    }
+    if (poison_j == j) HLP_K(launch_poison(lp));
   }
+  if (rs.mixed) {
+    HLP_K(launch_combine(lp));
+    HLP_K(launch_kkt_rows(lp));
+    HLP_K(launch_kkt_cols(lp, lp->rbuf));
+    HLP_K(launch_finalize(lp, 4 | 8, SLOT_CHECK));
+  } else {
+    HLP_K(launch_kkt_cols(lp, lp->rbuf));
+    HLP_K(launch_finalize(lp, 4, SLOT_CHECK));
+  }
+  return HLP_OK;
 }
 
-// ------------------------------------------------------------------ FP32 loop with refinement
-// Iterates and anchors are FP32 corrections around an FP64 centre:
-// x = xc + x'/P, y = yc + y'/D.  At every restart the centre moves to zhat
-// (FP64), P and D are recomputed from the FP64 violations and the FP32
-// correction data are rebuilt; the iteration is the same PDHG step with
-// tau' = tau P / D and sigma' = sigma D / P.
-hlp_err solve_mixed(hlp_lp* lp, const hlp_params& p, const double* x0, const double* y0, double* rout,
-                    double* trace, Ctl& c, Kkt& kk, int32_t& status) {
+// Capture a run of eval_freq iterations into a graph (once per handle and shape).
+hlp_err graph_for(hlp_lp* lp, const RunShape& rs, hipGraphExec_t* out) {
+  const int idx = (rs.mixed ? 2 : 0) + (rs.first_res ? 1 : 0);
+  if (lp->graph_len != rs.len) {
+    for (void*& g : lp->graph_exec)
+      if (g) {
+        HLP_HIP(hipGraphExecDestroy(static_cast<hipGraphExec_t>(g)));
+        g = nullptr;
+      }
+    lp->graph_len = rs.len;
+  }
+  if (!lp->graph_exec[idx]) {
+    if (!lp->capture_stream) HLP_HIP(hipStreamCreateWithFlags(&lp->capture_stream, hipStreamNonBlocking));
+    hipStream_t user = lp->stream;
+    lp->stream = lp->capture_stream;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(lp->capture_stream, hipStreamCaptureModeThreadLocal);
+    hlp_err r = HLP_OK;
+    if (e == hipSuccess) r = issue_run(lp, rs, nullptr, 0, 0, 0, -1);
+    hipError_t e2 = hipStreamEndCapture(lp->capture_stream, &g);
+    lp->stream = user;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    if (r != HLP_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return r;
+    }
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    lp->graph_exec[idx] = ex;
+  }
+  *out = static_cast<hipGraphExec_t>(lp->graph_exec[idx]);
+  return HLP_OK;
+}
+
+// ------------------------------------------------------------------ the loop (both precisions)
+hlp_err run_loop(hlp_lp* lp, const hlp_params& p, const double* x0, const double* y0, double* trace, Ctl& c,
+                 Kkt& kk, int32_t& status) {
+  const bool mixed = p.precision == HLP_MIXED;
   const double eta = lp->eta;
   const int64_t tstride = 2 * (int64_t)lp->n + 2 * (int64_t)lp->m;
-  // centre at the start point
   HLP_K(launch_warm_start(lp, x0, y0));
-  if (lp->n) HLP_HIP(hipMemcpyAsync(lp->xh, lp->x, sizeof(double) * lp->n, hipMemcpyDeviceToDevice, lp->stream));
-  if (lp->m) HLP_HIP(hipMemcpyAsync(lp->yh, lp->y, sizeof(double) * lp->m, hipMemcpyDeviceToDevice, lp->stream));
-  HLP_K(launch_kkt_rows(lp, SLOT_TMP));
-  HLP_K(launch_kkt_cols(lp, SLOT_TMP, nullptr));
   double P = 1.0, D = 1.0;
-  HLP_K(launch_recentre(lp, P, D));
-  c.omega = p.omega0;  // original units; the FP32 step uses omega' = omega D / P
-  bool r0_pending = false;
+  if (mixed) {
+    // the first centre is the start point, with P = D = 1
+    if (lp->n) HLP_HIP(hipMemcpyAsync(lp->xh, lp->x, sizeof(double) * lp->n, hipMemcpyDeviceToDevice, lp->stream));
+    if (lp->m) HLP_HIP(hipMemcpyAsync(lp->yh, lp->y, sizeof(double) * lp->m, hipMemcpyDeviceToDevice, lp->stream));
+    HLP_K(launch_kkt_rows(lp));
+    HLP_K(launch_kkt_cols(lp, nullptr));
+    HLP_K(launch_recentre(lp, P, D));
+  }
+  c.omega = p.omega0;  // in the FP32 path, omega in original units; the step uses omega D / P
   double R[NSLOT * NQ];
   const double t_start = now_s();
   while (true) {
-    const double om = c.omega * D / P;
-    const double tau = eta / om, sigma = eta * om;
-    const bool check = ((c.t + 1) % p.eval_freq == 0) || (c.t + 1 == p.max_iter);
-    const bool need_r = (c.k == 0) || check;
+    const int64_t next = std::min<int64_t>((c.t / p.eval_freq + 1) * p.eval_freq, p.max_iter);
+    RunShape rs{(int32_t)(next - c.t), c.k == 0, mixed};
+    const double om = mixed ? c.omega * D / P : c.omega;
+    HLP_K(launch_set_step(lp, eta / om, eta * om, p.gamma, c.k, P, D));
+    const int32_t poison_j =
+        (p.debug_poison_iter > c.t && p.debug_poison_iter <= next) ? (int32_t)(p.debug_poison_iter - c.t - 1) : -1;
     const bool traced = trace && c.t < p.trace_iters;
-    StepArgs s{tau, sigma, (double)(c.k + 1) / (double)(c.k + 2), p.gamma, (need_r || traced) ? 1 : 0, 0};
-    HLP_K(launch_primal32(lp, s));
-    HLP_K(launch_dual32(lp, s));
-    if (need_r) {
-      HLP_K(launch_finalize(lp, 1 | 2 | 16, check ? SLOT_CHECK : SLOT_R0));
-      if (!check) r0_pending = true;
+    if (p.graphs && rs.len == p.eval_freq && rs.len > 1 && !traced && poison_j < 0) {
+      hipGraphExec_t ex = nullptr;
+      HLP_TRY(graph_for(lp, rs, &ex));
+      HLP_HIP(hipGraphLaunch(ex, lp->stream));
+    } else {
+      HLP_TRY(issue_run(lp, rs, trace, c.t, trace ? p.trace_iters : 0, tstride, poison_j));
     }
-    if (traced) HLP_K(launch_trace32(lp, trace + c.t * tstride, P, D));
-    const bool epoch_start = c.k == 0;
-    ++c.k;
-    ++c.t;
-    if (!check) continue;
-    HLP_K(launch_combine(lp, P, D));
-    HLP_K(launch_kkt_rows(lp, SLOT_CHECK));
-    HLP_K(launch_kkt_cols(lp, SLOT_CHECK, rout));
-    HLP_K(launch_finalize(lp, 4 | 8, SLOT_CHECK));
-    HLP_TRY(read_results(lp, R));
+    HLP_HIP(hipMemcpyAsync(R, lp->results, sizeof(R), hipMemcpyDeviceToHost, lp->stream));
+    HLP_HIP(hipStreamSynchronize(lp->stream));
+    c.t = next;
+    c.k += rs.len;
     ++c.checks;
     const double* RC = R + SLOT_CHECK * NQ;
     const double r = fixed_point_residual(RC, eta, om);
-    if (epoch_start) {
-      c.r0 = r;
-    } else if (r0_pending) {
-      c.r0 = fixed_point_residual(R + SLOT_R0 * NQ, eta, om);
-    }
-    r0_pending = false;
+    if (rs.first_res) c.r0 = rs.len == 1 ? r : fixed_point_residual(R + SLOT_R0 * NQ, eta, om);
     kk = kkt_from(RC, lp);
     status = -1;
     if (!kk.finite || !std::isfinite(r)) status = HLP_NUMERICAL;
@@ -231,11 +245,16 @@ hlp_err solve_mixed(hlp_lp* lp, const hlp_params& p, const double* x0, const dou
     if (restart_test(r, c.r0, c.r_prev, c.k, c.t, p)) {
       ++c.restarts;
       const double om_new = pid_update(om, std::sqrt(RC[Q_XA2]), std::sqrt(RC[Q_YA2]), c, p);
-      c.omega = om_new * P / D;
-      // refinement: re-centre at zhat and rescale from the FP64 violations there
-      P = pow2_scale(std::max(RC[Q_VP], RC[Q_VX]), P);
-      D = pow2_scale(RC[Q_VD], D);
-      HLP_K(launch_recentre(lp, P, D));
+      if (mixed) {
+        c.omega = om_new * P / D;
+        // refinement: re-centre at zhat and rescale from the FP64 violations there
+        P = pow2_scale(std::max(RC[Q_VP], RC[Q_VX]), P);
+        D = pow2_scale(RC[Q_VD], D);
+        HLP_K(launch_recentre(lp, P, D));
+      } else {
+        c.omega = om_new;
+        HLP_K(launch_restart_copy(lp, p.restart_to_current));
+      }
       c.k = 0;
       c.r_prev = kInf;
     } else {
@@ -266,14 +285,18 @@ hlp_err hlp_solve(hlp_lp* lp, const hlp_params* pp, const double* x0, const doub
     set_error("hlp_solve: precision differs from the one the handle was created with");
     return HLP_EUNSUPPORTED;
   }
+  if (p.precision == HLP_MIXED && p.restart_to_current) {
+    set_error("hlp_solve: the FP32 path re-centres at zhat; restart_to_current must be 0");
+    return HLP_EUNSUPPORTED;
+  }
   const double t0 = now_s();
   Ctl c;
   Kkt kk{};
   int32_t status = -1;
-  hlp_err e = p.precision == HLP_MIXED ? solve_mixed(lp, p, x0, y0, r, trace, c, kk, status)
-                                       : solve_fp64(lp, p, x0, y0, r, trace, c, kk, status);
-  if (e != HLP_OK) return e;
+  HLP_TRY(run_loop(lp, p, x0, y0, trace, c, kk, status));
   HLP_HIP(launch_unscale(lp, x, y));
+  if (r && lp->n)
+    HLP_HIP(hipMemcpyAsync(r, lp->rbuf, sizeof(double) * lp->n, hipMemcpyDeviceToDevice, lp->stream));
   HLP_HIP(hipStreamSynchronize(lp->stream));
   if (info) {
     info->status = status;
@@ -312,23 +335,25 @@ hlp_err hlp_profile_iterations(hlp_lp* lp, const hlp_params* pp, int32_t iters, 
   if (mixed) {
     if (lp->n) HLP_HIP(hipMemcpyAsync(lp->xh, lp->x, sizeof(double) * lp->n, hipMemcpyDeviceToDevice, lp->stream));
     if (lp->m) HLP_HIP(hipMemcpyAsync(lp->yh, lp->y, sizeof(double) * lp->m, hipMemcpyDeviceToDevice, lp->stream));
-    HLP_HIP(launch_kkt_rows(lp, SLOT_TMP));
-    HLP_HIP(launch_kkt_cols(lp, SLOT_TMP, nullptr));
+    HLP_HIP(launch_kkt_rows(lp));
+    HLP_HIP(launch_kkt_cols(lp, nullptr));
     HLP_HIP(launch_recentre(lp, 1.0, 1.0));
   }
+  const double eta = lp->eta, om = p.omega0;
+  HLP_HIP(launch_set_step(lp, eta / om, eta * om, p.gamma, 0, 1.0, 1.0));
   std::vector<hipEvent_t> ev(2 * (size_t)iters + 1);
   for (auto& e : ev) HLP_HIP(hipEventCreate(&e));
-  const double eta = lp->eta, om = p.omega0;
   HLP_HIP(hipEventRecord(ev[0], lp->stream));
   for (int32_t i = 0; i < iters; ++i) {
-    StepArgs s{eta / om, eta * om, (double)(i + 1) / (double)(i + 2), p.gamma, 0, 0};
+    StepArgs s;
+    s.j = i;
     HLP_HIP(mixed ? launch_primal32(lp, s) : launch_primal(lp, s));
     HLP_HIP(hipEventRecord(ev[2 * i + 1], lp->stream));
     HLP_HIP(mixed ? launch_dual32(lp, s) : launch_dual(lp, s));
     HLP_HIP(hipEventRecord(ev[2 * i + 2], lp->stream));
   }
   HLP_HIP(hipStreamSynchronize(lp->stream));
-  double tp = 0.0, td = 0.0, tot = 0.0;
+  double tp = 0.0, td = 0.0;
   for (int32_t i = 0; i < iters; ++i) {
     float a = 0.f, b = 0.f;
     HLP_HIP(hipEventElapsedTime(&a, ev[2 * i], ev[2 * i + 1]));
@@ -338,11 +363,10 @@ hlp_err hlp_profile_iterations(hlp_lp* lp, const hlp_params* pp, int32_t iters, 
   }
   float all = 0.f;
   HLP_HIP(hipEventElapsedTime(&all, ev[0], ev[2 * (size_t)iters]));
-  tot = all;
-  for (auto& e : ev) hipEventDestroy(e);
+  for (auto& e : ev) (void)hipEventDestroy(e);
   ms_out[0] = tp / iters;
   ms_out[1] = td / iters;
-  ms_out[2] = tot / iters;
+  ms_out[2] = (double)all / iters;
   ms_out[3] = iters;
   return HLP_OK;
 }

@@ -75,4 +75,50 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NQV], double* out
   }
 }
 
+// ---------------------------------------------------------------- row blocks
+// The hot SpMVs walk "row blocks" built at setup: each block covers at most
+// kRbRows consecutive rows whose nonzeros start in the same kRbCap-sized chunk
+// of the value array, and a row longer than kRbCap forms a block of its own.
+// So a block of short rows holds at most 2 kRbCap = kRbLds nonzeros, staged in
+// LDS; a long row is reduced by the whole block.
+constexpr int kRbRows = kBlock;
+constexpr int kRbCap = 2048;
+constexpr int kRbLds = 2 * kRbCap;
+
+template <typename T>
+__device__ __forceinline__ T block_sum_to0(T v) {
+  __shared__ T sh[kWaves];
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  T r = sh[0];
+  for (int k = 1; k < kWaves; ++k) r += sh[k];
+  __syncthreads();
+  return r;  // every thread gets the block sum
+}
+
+// Row sums of val .* vec[idx] over the calling block's rows [s, e) with
+// nonzeros [ps, pe).  In a block of short rows thread t returns the sum of
+// row s + t (products staged in LDS, then summed left to right); in a
+// single-row block every thread returns that row's sum (strided partials, a
+// fixed shuffle tree and the waves in order).  Deterministic either way.
+template <typename ACC, typename V, typename X>
+__device__ __forceinline__ ACC rb_dot(const int32_t* __restrict__ idx, const V* __restrict__ val,
+                                      const X* __restrict__ vec, int ps, int pe, int a0, int a1,
+                                      bool own, ACC* lds) {
+  const int tid = threadIdx.x;
+  if (pe - ps <= kRbLds) {
+    for (int q = ps + tid; q < pe; q += kBlock) lds[q - ps] = (ACC)val[q] * (ACC)vec[idx[q]];
+    __syncthreads();
+    ACC acc = 0;
+    if (own)
+      for (int q = a0 - ps; q < a1 - ps; ++q) acc += lds[q];
+    __syncthreads();
+    return acc;
+  }
+  ACC part = 0;
+  for (int q = ps + tid; q < pe; q += kBlock) part += (ACC)val[q] * (ACC)vec[idx[q]];
+  return block_sum_to0(part);
+}
+
 }  // namespace hlp

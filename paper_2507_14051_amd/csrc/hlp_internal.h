@@ -47,6 +47,13 @@ struct PowerState {
   int32_t pad;
 };
 
+// Step scalars read by the half-step kernels from device memory.
+struct StepDev {
+  double tau, sigma, gamma;
+  int64_t k0;  // Halpern index of launch offset j = 0
+  double P, D; // refinement scales of the FP32 path (x = xc + x'/P, y = yc + y'/D)
+};
+
 }  // namespace hlp
 
 struct hlp_lp {
@@ -63,7 +70,15 @@ struct hlp_lp {
   float* tval32 = nullptr;
   double* val0 = nullptr;   // unscaled CSR values (kept to rescale after a vector update? no: for stats)
   double* tval0 = nullptr;  // unscaled transpose values
-  int32_t Lr = 8, Lc = 8;   // lanes per row for A~ and A~^T
+  int32_t Lr = 8, Lc = 8;   // lanes per row for A~ and A~^T (setup and check-only kernels)
+  // row blocks (see device.h) of A~ (rbA, nbA blocks) and of A~^T (rbT, nbT)
+  int32_t *rbA = nullptr, *rbT = nullptr, *rbtmp = nullptr;
+  int32_t nbA = 0, nbT = 0;
+  hlp::StepDev* step = nullptr;
+  // captured runs of eval_freq iterations (see controller.cpp)
+  void* graph_exec[4] = {nullptr, nullptr, nullptr, nullptr};
+  int32_t graph_len = 0;
+  hipStream_t capture_stream = nullptr;
   // scaling diagonals and scaled vectors
   double *dr = nullptr, *dc = nullptr;
   double *ct = nullptr, *lct = nullptr, *uct = nullptr, *lvt = nullptr, *uvt = nullptr;
@@ -137,16 +152,20 @@ hipError_t launch_fill32(float* p, float v, int64_t n, hipStream_t s);
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 
 // Iteration (kernels_iter.hip).
+// The step scalars (tau, sigma, gamma, k0) are set on the device by
+// launch_set_step; each half-step launch carries its offset j from k0.
 struct StepArgs {
-  double tau, sigma, a, gamma;
-  int32_t residual;          // compute the check quantities and write xhat / yhat
-  int32_t slot;              // result slot for the finalize
+  int32_t j = 0;
+  int32_t residual = 0;      // compute the check quantities and write xhat / yhat
   uint8_t* mask_x = nullptr; // if set (FP64 only): write xhat and the clamp codes of v
   uint8_t* mask_y = nullptr; // if set (FP64 only): write yhat and the clamp codes of w
 };
+hipError_t launch_build_row_blocks(hlp_lp* lp, const int32_t* ptr, int32_t rows, int32_t* rb, int32_t* count);
+hipError_t launch_set_step(hlp_lp* lp, double tau, double sigma, double gamma, int64_t k0, double P = 1.0,
+                           double D = 1.0);
 hipError_t launch_primal(hlp_lp* lp, const StepArgs& s);
 hipError_t launch_dual(hlp_lp* lp, const StepArgs& s);
-hipError_t launch_kkt_cols(hlp_lp* lp, int32_t slot, double* r_out);
+hipError_t launch_kkt_cols(hlp_lp* lp, double* r_out);
 hipError_t launch_finalize(hlp_lp* lp, int32_t which /*0 primal,1 dual,2 kkt*/, int32_t slot);
 hipError_t launch_restart_copy(hlp_lp* lp, int32_t to_current);
 hipError_t launch_warm_start(hlp_lp* lp, const double* x0, const double* y0);
@@ -157,11 +176,11 @@ hipError_t launch_poison(hlp_lp* lp);
 // Mixed precision (kernels_iter.hip).
 hipError_t launch_primal32(hlp_lp* lp, const StepArgs& s);
 hipError_t launch_dual32(hlp_lp* lp, const StepArgs& s);
-hipError_t launch_combine(hlp_lp* lp, double P, double D);  // xh <- xcen + xh32/P, yh <- ...
-hipError_t launch_kkt_rows(hlp_lp* lp, int32_t slot);        // A~ xh (FP64) and row KKT terms
+hipError_t launch_combine(hlp_lp* lp);  // xh <- xcen + xh32/P, yh <- ycen + yh32/D (P, D from the step)
+hipError_t launch_kkt_rows(hlp_lp* lp);                      // A~ xh (FP64) and row KKT terms
 hipError_t launch_recentre(hlp_lp* lp, double P, double D);  // rebuild the correction data
 hipError_t launch_zero_mixed(hlp_lp* lp);
-hipError_t launch_trace32(hlp_lp* lp, double* dst, double P, double D);
+hipError_t launch_trace32(hlp_lp* lp, double* dst);
 
 // Adjoint (kernels_adjoint.hip).  Reverse mode of one iteration; mode of the
 // iteration: 0 Halpern update after it, 1 restart after it, 2 the last one.

@@ -28,50 +28,67 @@ constexpr int kRegionStride = 8;
 inline double* region(hlp_lp* lp, int r) { return lp->partials + (int64_t)r * lp->partial_blocks * kRegionStride; }
 enum { R_PRIMAL = 0, R_DUAL = 1, R_KKT = 2, R_ROWS = 3 };
 
-// ============================================================================ FP64
+// ============================================================================ step scalars
+// tau, sigma, gamma and the Halpern index k0 at the start of the current run
+// of launches live in device memory, so a run of iterations can be replayed
+// from a HIP graph; each launch carries only its offset j (a = (k0+j+1)/(k0+j+2)).
+__global__ void k_set_step(StepDev* s, double tau, double sigma, double gamma, int64_t k0, double P, double D) {
+  s->tau = tau;
+  s->sigma = sigma;
+  s->gamma = gamma;
+  s->k0 = k0;
+  s->P = P;
+  s->D = D;
+}
+
+__device__ __forceinline__ double halpern_a(const StepDev* s, int32_t j) {
+  const int64_t k = s->k0 + j;
+  return (double)(k + 1) / (double)(k + 2);
+}
+
+// ============================================================================ FP64 half-steps
 struct PrimalArgs {
-  const int32_t* cp; const int32_t* row; const double* tval;
+  const int32_t* rb; const int32_t* cp; const int32_t* row; const double* tval;
   const double* y; double* x; const double* xa; const double* ct; const double* lv; const double* uv;
-  double* xbar; double* xh; double* dx; double* partials; uint8_t* mask;
-  int32_t n; double tau, a, gamma;
+  double* xbar; double* xh; double* dx; double* partials; uint8_t* mask; const StepDev* step;
+  int32_t j;
 };
 
 // MODE 0: plain step; 1: also xhat, x - xhat and the check partials;
 // 2: also xhat and the clamp code of v (for the reverse mode).
-template <int L, int MODE>
+template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_primal(PrimalArgs p) {
   constexpr bool RES = MODE == 1;
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t j = t / L;
-  const int lane = threadIdx.x & (L - 1);
-  const double* __restrict__ tval = p.tval;
-  const int32_t* __restrict__ row = p.row;
-  const double* __restrict__ y = p.y;
-  double acc = 0.0;
-  if (j < p.n) {
-    const int s = p.cp[j], e = p.cp[j + 1];
-    for (int q = s + lane; q < e; q += L) acc += tval[q] * y[row[q]];
+  __shared__ double lds[kRbLds];
+  const int s = p.rb[blockIdx.x], e = p.rb[blockIdx.x + 1];
+  const int j = s + threadIdx.x;
+  const bool own = j < e;
+  double xj = 0.0, cj = 0.0, lo = 0.0, hi = 0.0, xaj = 0.0;
+  int a0 = 0, a1 = 0;
+  if (own) {
+    xj = p.x[j]; cj = p.ct[j]; lo = p.lv[j]; hi = p.uv[j]; xaj = p.xa[j];
+    a0 = p.cp[j]; a1 = p.cp[j + 1];
   }
-  acc = group_sum<L>(acc);
+  const int ps = p.cp[s], pe = p.cp[e];
+  const double g = rb_dot<double>(p.row, p.tval, p.y, ps, pe, a0, a1, own, lds);
   double q0 = 0.0, q1 = 0.0;
-  if (j < p.n && lane == 0) {
-    const double xj = p.x[j];
-    const double v = xj - p.tau * (p.ct[j] - acc);
-    const double xh = clampv(v, p.lv[j], p.uv[j]);
+  if (own) {
+    const double tau = p.step->tau, gam = p.step->gamma, a = halpern_a(p.step, p.j);
+    const double v = xj - tau * (cj - g);
+    const double xh = clampv(v, lo, hi);
     p.xbar[j] = 2.0 * xh - xj;
-    const double xaj = p.xa[j];
-    p.x[j] = p.a * ((1.0 + p.gamma) * xh - p.gamma * xj) + (1.0 - p.a) * xaj;
+    p.x[j] = a * ((1.0 + gam) * xh - gam * xj) + (1.0 - a) * xaj;
     if (MODE == 2) {
       p.xh[j] = xh;
-      p.mask[j] = clamp_code(v, p.lv[j], p.uv[j]);
+      p.mask[j] = clamp_code(v, lo, hi);
     }
     if (RES) {
       p.xh[j] = xh;
       const double d = xj - xh;
       p.dx[j] = d;
       q0 = d * d;
-      const double e = xh - xaj;
-      q1 = e * e;
+      const double e2 = xh - xaj;
+      q1 = e2 * e2;
     }
   }
   if (RES) {
@@ -81,49 +98,41 @@ __global__ __launch_bounds__(kBlock) void k_primal(PrimalArgs p) {
 }
 
 struct DualArgs {
-  const int32_t* rp; const int32_t* col; const double* val;
+  const int32_t* rb; const int32_t* rp; const int32_t* col; const double* val;
   const double* xbar; const double* dx; const double* xh;
   double* y; const double* ya; const double* lc; const double* uc; const double* dr;
-  double* yh; double* partials; uint8_t* mask;
-  int32_t m; double sigma, a, gamma;
+  double* yh; double* partials; uint8_t* mask; const StepDev* step;
+  int32_t j;
 };
 
 // MODE as for k_primal (the code is that of w against the row bounds).
-template <int L, int MODE>
+template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_dual(DualArgs p) {
   constexpr bool RES = MODE == 1;
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t i = t / L;
-  const int lane = threadIdx.x & (L - 1);
-  const double* __restrict__ val = p.val;
-  const int32_t* __restrict__ col = p.col;
-  const double* __restrict__ xbar = p.xbar;
-  double acc = 0.0, adx = 0.0, axh = 0.0;
-  if (i < p.m) {
-    const int s = p.rp[i], e = p.rp[i + 1];
-    for (int q = s + lane; q < e; q += L) {
-      const double v = val[q];
-      const int c = col[q];
-      acc += v * xbar[c];
-      if (RES) {
-        adx += v * p.dx[c];
-        axh += v * p.xh[c];
-      }
-    }
+  __shared__ double lds[kRbLds];
+  const int s = p.rb[blockIdx.x], e = p.rb[blockIdx.x + 1];
+  const int i = s + threadIdx.x;
+  const bool own = i < e;
+  double yi = 0.0, lo = 0.0, hi = 0.0, yai = 0.0, dri = 1.0;
+  int a0 = 0, a1 = 0;
+  if (own) {
+    yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i];
+    if (RES) dri = p.dr[i];
+    a0 = p.rp[i]; a1 = p.rp[i + 1];
   }
-  acc = group_sum<L>(acc);
+  const int ps = p.rp[s], pe = p.rp[e];
+  const double h = rb_dot<double>(p.col, p.val, p.xbar, ps, pe, a0, a1, own, lds);
+  double adx = 0.0, axh = 0.0;
   if (RES) {
-    adx = group_sum<L>(adx);
-    axh = group_sum<L>(axh);
+    adx = rb_dot<double>(p.col, p.val, p.dx, ps, pe, a0, a1, own, lds);
+    axh = rb_dot<double>(p.col, p.val, p.xh, ps, pe, a0, a1, own, lds);
   }
   double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (i < p.m && lane == 0) {
-    const double yi = p.y[i];
-    const double lo = p.lc[i], hi = p.uc[i];
-    const double w = acc - yi / p.sigma;
-    const double yh = p.sigma * (clampv(w, lo, hi) - w);
-    const double yai = p.ya[i];
-    p.y[i] = p.a * ((1.0 + p.gamma) * yh - p.gamma * yi) + (1.0 - p.a) * yai;
+  if (own) {
+    const double sigma = p.step->sigma, gam = p.step->gamma, a = halpern_a(p.step, p.j);
+    const double w = h - yi / sigma;
+    const double yh = sigma * (clampv(w, lo, hi) - w);
+    p.y[i] = a * ((1.0 + gam) * yh - gam * yi) + (1.0 - a) * yai;
     if (MODE == 2) {
       p.yh[i] = yh;
       p.mask[i] = clamp_code(w, lo, hi);
@@ -133,9 +142,9 @@ __global__ __launch_bounds__(kBlock) void k_dual(DualArgs p) {
       const double dy = yi - yh;
       q[0] = dy * dy;
       q[1] = dy * adx;
-      const double e = yh - yai;
-      q[2] = e * e;
-      const double pr = (axh - clampv(axh, lo, hi)) / p.dr[i];
+      const double e2 = yh - yai;
+      q[2] = e2 * e2;
+      const double pr = (axh - clampv(axh, lo, hi)) / dri;
       q[3] = pr * pr;
       q[4] = (finite(lo) ? lo * fmax(yh, 0.0) : 0.0) - (finite(hi) ? hi * fmax(-yh, 0.0) : 0.0);
     }
@@ -148,32 +157,32 @@ __global__ __launch_bounds__(kBlock) void k_dual(DualArgs p) {
 // c~^T xhat; in mixed mode also the max dual violation |g~ - r~| and the max
 // bound violation of xhat (scaled space), and A~^T yhat itself.
 struct KktColArgs {
-  const int32_t* cp; const int32_t* row; const double* tval;
+  const int32_t* rb; const int32_t* cp; const int32_t* row; const double* tval;
   const double* yh; const double* xh; const double* ct; const double* lv; const double* uv;
   const double* dc; double* r_out; double* aty_out; double* partials;
-  int32_t n;
 };
 
-template <int L, bool MIXED>
+template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_kkt_cols(KktColArgs p) {
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t j = t / L;
-  const int lane = threadIdx.x & (L - 1);
-  double acc = 0.0;
-  if (j < p.n) {
-    const int s = p.cp[j], e = p.cp[j + 1];
-    for (int q = s + lane; q < e; q += L) acc += p.tval[q] * p.yh[p.row[q]];
+  __shared__ double lds[kRbLds];
+  const int s = p.rb[blockIdx.x], e = p.rb[blockIdx.x + 1];
+  const int j = s + threadIdx.x;
+  const bool own = j < e;
+  int a0 = 0, a1 = 0;
+  if (own) {
+    a0 = p.cp[j];
+    a1 = p.cp[j + 1];
   }
-  acc = group_sum<L>(acc);
+  const double acc = rb_dot<double>(p.row, p.tval, p.yh, p.cp[s], p.cp[e], a0, a1, own, lds);
   double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (j < p.n && lane == 0) {
+  if (own) {
     const double g = p.ct[j] - acc;
     const double lo = p.lv[j], hi = p.uv[j];
     const bool fl = finite(lo), fu = finite(hi);
     const double r = (fl && fu) ? g : (fl ? fmax(g, 0.0) : (fu ? fmin(g, 0.0) : 0.0));
     const double d = p.dc[j];
-    const double e = (g - r) / d;
-    q[0] = e * e;
+    const double e2 = (g - r) / d;
+    q[0] = e2 * e2;
     q[1] = (fl ? lo * fmax(r, 0.0) : 0.0) - (fu ? hi * fmax(-r, 0.0) : 0.0);
     const double xj = p.xh[j];
     q[2] = p.ct[j] * xj;
@@ -196,25 +205,24 @@ __global__ __launch_bounds__(kBlock) void k_kkt_cols(KktColArgs p) {
 // A~ xh, ||(A~xh - proj)/d_r||^2, the row dual-objective part, the max
 // primal violation (scaled); stores A~ xh.
 struct KktRowArgs {
-  const int32_t* rp; const int32_t* col; const double* val;
+  const int32_t* rb; const int32_t* rp; const int32_t* col; const double* val;
   const double* xh; const double* yh; const double* lc; const double* uc; const double* dr;
   double* ax_out; double* partials;
-  int32_t m;
 };
 
-template <int L>
 __global__ __launch_bounds__(kBlock) void k_kkt_rows(KktRowArgs p) {
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t i = t / L;
-  const int lane = threadIdx.x & (L - 1);
-  double acc = 0.0;
-  if (i < p.m) {
-    const int s = p.rp[i], e = p.rp[i + 1];
-    for (int q = s + lane; q < e; q += L) acc += p.val[q] * p.xh[p.col[q]];
+  __shared__ double lds[kRbLds];
+  const int s = p.rb[blockIdx.x], e = p.rb[blockIdx.x + 1];
+  const int i = s + threadIdx.x;
+  const bool own = i < e;
+  int a0 = 0, a1 = 0;
+  if (own) {
+    a0 = p.rp[i];
+    a1 = p.rp[i + 1];
   }
-  acc = group_sum<L>(acc);
+  const double acc = rb_dot<double>(p.col, p.val, p.xh, p.rp[s], p.rp[e], a0, a1, own, lds);
   double q[3] = {0.0, 0.0, 0.0};
-  if (i < p.m && lane == 0) {
+  if (own) {
     const double lo = p.lc[i], hi = p.uc[i];
     const double viol = acc - clampv(acc, lo, hi);
     const double pr = viol / p.dr[i];
@@ -231,39 +239,41 @@ __global__ __launch_bounds__(kBlock) void k_kkt_rows(KktRowArgs p) {
 // Shifted coordinates x = xc + x'/P, y = yc + y'/D; the step on (x', y') is
 // the same PDHG step with tau' = tau P/D, sigma' = sigma D/P and data
 // (c', lv', uv', lc', uc', b):  yhat' = y' + sigma'(clamp(h - (b + y')/sigma') - h).
+// Products and sums in FP32; the check partials accumulate in FP64.
 struct Primal32Args {
-  const int32_t* cp; const int32_t* row; const float* tval;
+  const int32_t* rb; const int32_t* cp; const int32_t* row; const float* tval;
   const float* y; float* x; const float* xa; const float* c; const float* lv; const float* uv;
-  float* xbar; float* xh; float* dx; double* partials;
-  int32_t n; float tau, a, gamma;
+  float* xbar; float* xh; float* dx; double* partials; const StepDev* step;
+  int32_t j;
 };
 
-template <int L, bool RES>
+template <bool RES>
 __global__ __launch_bounds__(kBlock) void k_primal32(Primal32Args p) {
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t j = t / L;
-  const int lane = threadIdx.x & (L - 1);
-  float acc = 0.0f;
-  if (j < p.n) {
-    const int s = p.cp[j], e = p.cp[j + 1];
-    for (int q = s + lane; q < e; q += L) acc += p.tval[q] * p.y[p.row[q]];
+  __shared__ float lds[kRbLds];
+  const int s = p.rb[blockIdx.x], e = p.rb[blockIdx.x + 1];
+  const int j = s + threadIdx.x;
+  const bool own = j < e;
+  float xj = 0.0f, cj = 0.0f, lo = 0.0f, hi = 0.0f, xaj = 0.0f;
+  int a0 = 0, a1 = 0;
+  if (own) {
+    xj = p.x[j]; cj = p.c[j]; lo = p.lv[j]; hi = p.uv[j]; xaj = p.xa[j];
+    a0 = p.cp[j]; a1 = p.cp[j + 1];
   }
-  acc = group_sum<L>(acc);
+  const float g = rb_dot<float>(p.row, p.tval, p.y, p.cp[s], p.cp[e], a0, a1, own, lds);
   double q0 = 0.0, q1 = 0.0;
-  if (j < p.n && lane == 0) {
-    const float xj = p.x[j];
-    const float v = xj - p.tau * (p.c[j] - acc);
-    const float xh = clampv(v, p.lv[j], p.uv[j]);
+  if (own) {
+    const float tau = (float)p.step->tau, gam = (float)p.step->gamma, a = (float)halpern_a(p.step, p.j);
+    const float v = xj - tau * (cj - g);
+    const float xh = clampv(v, lo, hi);
     p.xbar[j] = 2.0f * xh - xj;
-    const float xaj = p.xa[j];
-    p.x[j] = p.a * ((1.0f + p.gamma) * xh - p.gamma * xj) + (1.0f - p.a) * xaj;
+    p.x[j] = a * ((1.0f + gam) * xh - gam * xj) + (1.0f - a) * xaj;
     if (RES) {
       p.xh[j] = xh;
       const float d = xj - xh;
       p.dx[j] = d;
       q0 = (double)d * (double)d;
-      const double e = (double)(xh - xaj);
-      q1 = e * e;
+      const double e2 = (double)(xh - xaj);
+      q1 = e2 * e2;
     }
   }
   if (RES) {
@@ -273,45 +283,42 @@ __global__ __launch_bounds__(kBlock) void k_primal32(Primal32Args p) {
 }
 
 struct Dual32Args {
-  const int32_t* rp; const int32_t* col; const float* val;
+  const int32_t* rb; const int32_t* rp; const int32_t* col; const float* val;
   const float* xbar; const float* dx;
   float* y; const float* ya; const float* lc; const float* uc; const float* b;
-  float* yh; double* partials;
-  int32_t m; float sigma, a, gamma;
+  float* yh; double* partials; const StepDev* step;
+  int32_t j;
 };
 
-template <int L, bool RES>
+template <bool RES>
 __global__ __launch_bounds__(kBlock) void k_dual32(Dual32Args p) {
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t i = t / L;
-  const int lane = threadIdx.x & (L - 1);
-  float acc = 0.0f;
-  double adx = 0.0;
-  if (i < p.m) {
-    const int s = p.rp[i], e = p.rp[i + 1];
-    for (int q = s + lane; q < e; q += L) {
-      const float v = p.val[q];
-      const int c = p.col[q];
-      acc += v * p.xbar[c];
-      if (RES) adx += (double)v * (double)p.dx[c];
-    }
+  __shared__ double lds[kRbLds];
+  const int s = p.rb[blockIdx.x], e = p.rb[blockIdx.x + 1];
+  const int i = s + threadIdx.x;
+  const bool own = i < e;
+  float yi = 0.0f, lo = 0.0f, hi = 0.0f, yai = 0.0f, bi = 0.0f;
+  int a0 = 0, a1 = 0;
+  if (own) {
+    yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i]; bi = p.b[i];
+    a0 = p.rp[i]; a1 = p.rp[i + 1];
   }
-  acc = group_sum<L>(acc);
-  if (RES) adx = group_sum<L>(adx);
+  const int ps = p.rp[s], pe = p.rp[e];
+  const float h = rb_dot<float>(p.col, p.val, p.xbar, ps, pe, a0, a1, own, reinterpret_cast<float*>(lds));
+  double adx = 0.0;
+  if (RES) adx = rb_dot<double>(p.col, p.val, p.dx, ps, pe, a0, a1, own, lds);
   double q[3] = {0.0, 0.0, 0.0};
-  if (i < p.m && lane == 0) {
-    const float yi = p.y[i];
-    const float w = acc - (p.b[i] + yi) / p.sigma;
-    const float yh = yi + p.sigma * (clampv(w, p.lc[i], p.uc[i]) - acc);
-    const float yai = p.ya[i];
-    p.y[i] = p.a * ((1.0f + p.gamma) * yh - p.gamma * yi) + (1.0f - p.a) * yai;
+  if (own) {
+    const float sigma = (float)p.step->sigma, gam = (float)p.step->gamma, a = (float)halpern_a(p.step, p.j);
+    const float w = h - (bi + yi) / sigma;
+    const float yh = yi + sigma * (clampv(w, lo, hi) - h);
+    p.y[i] = a * ((1.0f + gam) * yh - gam * yi) + (1.0f - a) * yai;
     if (RES) {
       p.yh[i] = yh;
       const double dy = (double)(yi - yh);
       q[0] = dy * dy;
       q[1] = dy * adx;
-      const double e = (double)(yh - yai);
-      q[2] = e * e;
+      const double e2 = (double)(yh - yai);
+      q[2] = e2 * e2;
     }
   }
   if (RES) block_reduce_store<3>(q, p.partials + (int64_t)blockIdx.x * kRegionStride);
@@ -369,9 +376,10 @@ __global__ void k_trace(const double* xh, const double* yh, const double* x, con
 }
 
 __global__ void k_trace32(const float* xh, const float* yh, const float* x, const float* y,
-                          const double* xc, const double* yc, double P, double D, double* dst,
+                          const double* xc, const double* yc, const StepDev* st, double* dst,
                           int32_t n, int32_t m) {
   int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const double P = st->P, D = st->D;
   if (i < n) {
     dst[i] = xc[i] + (double)xh[i] / P;
     dst[(int64_t)n + m + i] = xc[i] + (double)x[i] / P;
@@ -386,8 +394,9 @@ __global__ void k_poison(double* x) { x[0] = __builtin_nan(""); }
 
 // xh <- xc + xh32/P, yh <- yc + yh32/D (the FP64 point of the shifted iterate)
 __global__ void k_combine(const float* xh32, const float* yh32, const double* xc, const double* yc,
-                          double P, double D, double* xh, double* yh, int32_t n, int32_t m) {
+                          const StepDev* st, double* xh, double* yh, int32_t n, int32_t m) {
   int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const double P = st->P, D = st->D;
   if (i < n) xh[i] = xc[i] + (double)xh32[i] / P;
   if (i < m) yh[i] = yc[i] + (double)yh32[i] / D;
 }
@@ -452,70 +461,7 @@ __global__ void k_finalize(FinArgs a) {
   }
 }
 
-// ============================================================================ dispatch
-template <int L>
-struct PrimalL {
-  static hipError_t run(const PrimalArgs& a, int mode, int nb, hipStream_t s) {
-    if (mode == 1) hipLaunchKernelGGL((k_primal<L, 1>), dim3(nb), dim3(kBlock), 0, s, a);
-    else if (mode == 2) hipLaunchKernelGGL((k_primal<L, 2>), dim3(nb), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_primal<L, 0>), dim3(nb), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
-  }
-};
-template <int L>
-struct DualL {
-  static hipError_t run(const DualArgs& a, int mode, int nb, hipStream_t s) {
-    if (mode == 1) hipLaunchKernelGGL((k_dual<L, 1>), dim3(nb), dim3(kBlock), 0, s, a);
-    else if (mode == 2) hipLaunchKernelGGL((k_dual<L, 2>), dim3(nb), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_dual<L, 0>), dim3(nb), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
-  }
-};
-template <int L>
-struct Primal32L {
-  static hipError_t run(const Primal32Args& a, bool res, int nb, hipStream_t s) {
-    if (res) hipLaunchKernelGGL((k_primal32<L, true>), dim3(nb), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_primal32<L, false>), dim3(nb), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
-  }
-};
-template <int L>
-struct Dual32L {
-  static hipError_t run(const Dual32Args& a, bool res, int nb, hipStream_t s) {
-    if (res) hipLaunchKernelGGL((k_dual32<L, true>), dim3(nb), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_dual32<L, false>), dim3(nb), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
-  }
-};
-template <int L>
-struct KktColsL {
-  static hipError_t run(const KktColArgs& a, bool mixed, int nb, hipStream_t s) {
-    if (mixed) hipLaunchKernelGGL((k_kkt_cols<L, true>), dim3(nb), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_kkt_cols<L, false>), dim3(nb), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
-  }
-};
-template <int L>
-struct KktRowsL {
-  static hipError_t run(const KktRowArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_kkt_rows<L>), dim3(nb), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
-  }
-};
-
-template <template <int> class F, typename... Args>
-hipError_t dispatch_L(int L, Args... args) {
-  switch (L) {
-    case 1: return F<1>::run(args...);
-    case 2: return F<2>::run(args...);
-    case 4: return F<4>::run(args...);
-    case 8: return F<8>::run(args...);
-    case 16: return F<16>::run(args...);
-    case 32: return F<32>::run(args...);
-    default: return F<64>::run(args...);
-  }
-}
-
+// ============================================================================ dispatch helpers
 Region make_region(const double* p, int64_t nb, std::initializer_list<int> qs, uint32_t max_mask) {
   Region r{};
   r.p = p;
@@ -530,37 +476,48 @@ Region make_region(const double* p, int64_t nb, std::initializer_list<int> qs, u
 }  // namespace
 
 // ============================================================================ launchers
+hipError_t launch_set_step(hlp_lp* lp, double tau, double sigma, double gamma, int64_t k0, double P, double D) {
+  hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, lp->stream, lp->step, tau, sigma, gamma, k0, P, D);
+  return hipGetLastError();
+}
+
 hipError_t launch_primal(hlp_lp* lp, const StepArgs& s) {
-  if (lp->n == 0) return hipSuccess;
-  PrimalArgs a{lp->cp, lp->row, lp->tval, lp->y, lp->x, lp->xa, lp->ct, lp->lvt, lp->uvt,
-               lp->xbar, lp->xh, lp->dxv, region(lp, R_PRIMAL), s.mask_x, lp->n, s.tau, s.a, s.gamma};
-  const int mode = s.mask_x ? 2 : (s.residual ? 1 : 0);
-  return dispatch_L<PrimalL>(lp->Lc, a, mode, nblocks((int64_t)lp->n * lp->Lc), lp->stream);
+  if (lp->nbT == 0) return hipSuccess;
+  PrimalArgs a{lp->rbT, lp->cp, lp->row, lp->tval, lp->y, lp->x, lp->xa, lp->ct, lp->lvt, lp->uvt,
+               lp->xbar, lp->xh, lp->dxv, region(lp, R_PRIMAL), s.mask_x, lp->step, s.j};
+  const dim3 g(lp->nbT), b(kBlock);
+  if (s.mask_x) hipLaunchKernelGGL(k_primal<2>, g, b, 0, lp->stream, a);
+  else if (s.residual) hipLaunchKernelGGL(k_primal<1>, g, b, 0, lp->stream, a);
+  else hipLaunchKernelGGL(k_primal<0>, g, b, 0, lp->stream, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_dual(hlp_lp* lp, const StepArgs& s) {
-  if (lp->m == 0) return hipSuccess;
-  DualArgs a{lp->rp, lp->col, lp->val, lp->xbar, lp->dxv, lp->xh, lp->y, lp->ya, lp->lct, lp->uct,
-             lp->dr, lp->yh, region(lp, R_DUAL), s.mask_y, lp->m, s.sigma, s.a, s.gamma};
-  const int mode = s.mask_y ? 2 : (s.residual ? 1 : 0);
-  return dispatch_L<DualL>(lp->Lr, a, mode, nblocks((int64_t)lp->m * lp->Lr), lp->stream);
+  if (lp->nbA == 0) return hipSuccess;
+  DualArgs a{lp->rbA, lp->rp, lp->col, lp->val, lp->xbar, lp->dxv, lp->xh, lp->y, lp->ya, lp->lct, lp->uct,
+             lp->dr, lp->yh, region(lp, R_DUAL), s.mask_y, lp->step, s.j};
+  const dim3 g(lp->nbA), b(kBlock);
+  if (s.mask_y) hipLaunchKernelGGL(k_dual<2>, g, b, 0, lp->stream, a);
+  else if (s.residual) hipLaunchKernelGGL(k_dual<1>, g, b, 0, lp->stream, a);
+  else hipLaunchKernelGGL(k_dual<0>, g, b, 0, lp->stream, a);
+  return hipGetLastError();
 }
 
-hipError_t launch_kkt_cols(hlp_lp* lp, int32_t slot, double* r_out) {
-  (void)slot;
-  if (lp->n == 0) return hipSuccess;
-  const bool mixed = lp->precision == HLP_MIXED;
-  KktColArgs a{lp->cp, lp->row, lp->tval, lp->yh, lp->xh, lp->ct, lp->lvt, lp->uvt, lp->dc, r_out,
-               lp->atyc, region(lp, R_KKT), lp->n};
-  return dispatch_L<KktColsL>(lp->Lc, a, mixed, nblocks((int64_t)lp->n * lp->Lc), lp->stream);
+hipError_t launch_kkt_cols(hlp_lp* lp, double* r_out) {
+  if (lp->nbT == 0) return hipSuccess;
+  KktColArgs a{lp->rbT, lp->cp, lp->row, lp->tval, lp->yh, lp->xh, lp->ct, lp->lvt, lp->uvt, lp->dc, r_out,
+               lp->atyc, region(lp, R_KKT)};
+  if (lp->precision == HLP_MIXED) hipLaunchKernelGGL(k_kkt_cols<true>, dim3(lp->nbT), dim3(kBlock), 0, lp->stream, a);
+  else hipLaunchKernelGGL(k_kkt_cols<false>, dim3(lp->nbT), dim3(kBlock), 0, lp->stream, a);
+  return hipGetLastError();
 }
 
-hipError_t launch_kkt_rows(hlp_lp* lp, int32_t slot) {
-  (void)slot;
-  if (lp->m == 0) return hipSuccess;
-  KktRowArgs a{lp->rp, lp->col, lp->val, lp->xh, lp->yh, lp->lct, lp->uct, lp->dr, lp->axc,
-               region(lp, R_ROWS), lp->m};
-  return dispatch_L<KktRowsL>(lp->Lr, a, nblocks((int64_t)lp->m * lp->Lr), lp->stream);
+hipError_t launch_kkt_rows(hlp_lp* lp) {
+  if (lp->nbA == 0) return hipSuccess;
+  KktRowArgs a{lp->rbA, lp->rp, lp->col, lp->val, lp->xh, lp->yh, lp->lct, lp->uct, lp->dr, lp->axc,
+               region(lp, R_ROWS)};
+  hipLaunchKernelGGL(k_kkt_rows, dim3(lp->nbA), dim3(kBlock), 0, lp->stream, a);
+  return hipGetLastError();
 }
 
 // which: bit 0 primal region, bit 1 dual region, bit 2 KKT-cols region,
@@ -570,8 +527,7 @@ hipError_t launch_finalize(hlp_lp* lp, int32_t which, int32_t slot) {
   a.dst = lp->results + (int64_t)slot * NQ;
   int nr = 0;
   const bool f32 = (which & 16) != 0;
-  const int64_t nbp = lp->n ? nblocks((int64_t)lp->n * lp->Lc) : 0;
-  const int64_t nbd = lp->m ? nblocks((int64_t)lp->m * lp->Lr) : 0;
+  const int64_t nbp = lp->nbT, nbd = lp->nbA;
   if (which & 1) a.r[nr++] = make_region(region(lp, R_PRIMAL), nbp, {Q_DX2, Q_XA2}, 0u);
   if (which & 2) {
     if (f32) a.r[nr++] = make_region(region(lp, R_DUAL), nbd, {Q_DY2, Q_DYADX, Q_YA2}, 0u);
@@ -620,41 +576,43 @@ hipError_t launch_trace(hlp_lp* lp, double* dst) {
   return hipGetLastError();
 }
 
-hipError_t launch_trace32(hlp_lp* lp, double* dst, double P, double D) {
+hipError_t launch_trace32(hlp_lp* lp, double* dst) {
   int64_t N = lp->m > lp->n ? lp->m : lp->n;
   if (N == 0) return hipSuccess;
   hipLaunchKernelGGL(k_trace32, dim3(nblocks(N)), dim3(kBlock), 0, lp->stream, lp->xh32, lp->yh32, lp->x32,
-                     lp->y32, lp->xcen, lp->ycen, P, D, dst, lp->n, lp->m);
+                     lp->y32, lp->xcen, lp->ycen, (const StepDev*)lp->step, dst, lp->n, lp->m);
   return hipGetLastError();
 }
 
 hipError_t launch_poison(hlp_lp* lp) {
-  if (lp->n == 0) return hipSuccess;
-  if (lp->precision == HLP_MIXED) return hipSuccess;
+  if (lp->n == 0 || lp->precision == HLP_MIXED) return hipSuccess;
   hipLaunchKernelGGL(k_poison, dim3(1), dim3(1), 0, lp->stream, lp->x);
   return hipGetLastError();
 }
 
 hipError_t launch_primal32(hlp_lp* lp, const StepArgs& s) {
-  if (lp->n == 0) return hipSuccess;
-  Primal32Args a{lp->cp, lp->row, lp->tval32, lp->y32, lp->x32, lp->xa32, lp->c32, lp->lv32, lp->uv32,
-                 lp->xbar32, lp->xh32, lp->dx32, region(lp, R_PRIMAL), lp->n,
-                 (float)s.tau, (float)s.a, (float)s.gamma};
-  return dispatch_L<Primal32L>(lp->Lc, a, (bool)s.residual, nblocks((int64_t)lp->n * lp->Lc), lp->stream);
+  if (lp->nbT == 0) return hipSuccess;
+  Primal32Args a{lp->rbT, lp->cp, lp->row, lp->tval32, lp->y32, lp->x32, lp->xa32, lp->c32, lp->lv32, lp->uv32,
+                 lp->xbar32, lp->xh32, lp->dx32, region(lp, R_PRIMAL), lp->step, s.j};
+  if (s.residual) hipLaunchKernelGGL(k_primal32<true>, dim3(lp->nbT), dim3(kBlock), 0, lp->stream, a);
+  else hipLaunchKernelGGL(k_primal32<false>, dim3(lp->nbT), dim3(kBlock), 0, lp->stream, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_dual32(hlp_lp* lp, const StepArgs& s) {
-  if (lp->m == 0) return hipSuccess;
-  Dual32Args a{lp->rp, lp->col, lp->val32, lp->xbar32, lp->dx32, lp->y32, lp->ya32, lp->lc32, lp->uc32,
-               lp->b32, lp->yh32, region(lp, R_DUAL), lp->m, (float)s.sigma, (float)s.a, (float)s.gamma};
-  return dispatch_L<Dual32L>(lp->Lr, a, (bool)s.residual, nblocks((int64_t)lp->m * lp->Lr), lp->stream);
+  if (lp->nbA == 0) return hipSuccess;
+  Dual32Args a{lp->rbA, lp->rp, lp->col, lp->val32, lp->xbar32, lp->dx32, lp->y32, lp->ya32, lp->lc32, lp->uc32,
+               lp->b32, lp->yh32, region(lp, R_DUAL), lp->step, s.j};
+  if (s.residual) hipLaunchKernelGGL(k_dual32<true>, dim3(lp->nbA), dim3(kBlock), 0, lp->stream, a);
+  else hipLaunchKernelGGL(k_dual32<false>, dim3(lp->nbA), dim3(kBlock), 0, lp->stream, a);
+  return hipGetLastError();
 }
 
-hipError_t launch_combine(hlp_lp* lp, double P, double D) {
+hipError_t launch_combine(hlp_lp* lp) {
   int64_t N = lp->m > lp->n ? lp->m : lp->n;
   if (N == 0) return hipSuccess;
   hipLaunchKernelGGL(k_combine, dim3(nblocks(N)), dim3(kBlock), 0, lp->stream, lp->xh32, lp->yh32, lp->xcen,
-                     lp->ycen, P, D, lp->xh, lp->yh, lp->n, lp->m);
+                     lp->ycen, (const StepDev*)lp->step, lp->xh, lp->yh, lp->n, lp->m);
   return hipGetLastError();
 }
 

@@ -255,6 +255,33 @@ __global__ void k_gather_transpose(const int32_t* __restrict__ perm, const int32
   }
 }
 
+// ----------------------------------------------------------------- row blocks
+// Row r starts a block if r is a multiple of kRbRows, if its nonzeros start in
+// another kRbCap-sized chunk than those of row r-1, or if row r or row r-1 is
+// longer than kRbCap (long rows stand alone).
+__global__ void k_rb_flags(const int32_t* __restrict__ ptr, int32_t rows, int32_t* __restrict__ flags) {
+  int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (r >= rows) return;
+  int f = 1;
+  if (r > 0) {
+    const int p0 = ptr[r - 1], p1 = ptr[r], p2 = ptr[r + 1];
+    f = (r % kRbRows == 0) || (p1 / kRbCap != p0 / kRbCap) || (p1 - p0 > kRbCap) || (p2 - p1 > kRbCap);
+  }
+  flags[r] = f;
+}
+
+__global__ void k_rb_scatter(const int32_t* __restrict__ flags, const int32_t* __restrict__ pos, int32_t rows,
+                             int32_t* __restrict__ rb, int32_t* __restrict__ count) {
+  int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (r >= rows) return;
+  if (flags[r]) rb[pos[r]] = (int32_t)r;
+  if (r == rows - 1) {
+    const int total = pos[r] + flags[r];
+    rb[total] = rows;
+    *count = total;
+  }
+}
+
 // ----------------------------------------------------------------- rescaling
 // Per-row statistic of |d_r[i] a_ij d_c[j]| over a CSR (MAX or SUM), then
 // rho = sqrt(stat) (1 for an empty row).  Used for both A (rows) and A^T
@@ -568,6 +595,19 @@ hipError_t launch_transpose(hlp_lp* lp) {
   }
   hipLaunchKernelGGL(k_gather_transpose, dim3(nblocks(nnz)), dim3(kBlock), 0, s, vin, lp->rowof,
                      lp->val0, nnz, lp->row, lp->tval0);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_row_blocks(hlp_lp* lp, const int32_t* ptr, int32_t rows, int32_t* rb, int32_t* count) {
+  if (rows == 0) return hipSuccess;
+  hipStream_t s = lp->stream;
+  int32_t* flags = lp->rbtmp;
+  int32_t* pos = lp->rbtmp + ((int64_t)(lp->m > lp->n ? lp->m : lp->n) + 1);
+  hipLaunchKernelGGL(k_rb_flags, dim3(nblocks(rows)), dim3(kBlock), 0, s, ptr, rows, flags);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = scan_exclusive(flags, pos, rows, lp->scan_tmp, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rb_scatter, dim3(nblocks(rows)), dim3(kBlock), 0, s, flags, pos, rows, rb, count);
   return hipGetLastError();
 }
 

@@ -222,3 +222,34 @@ def test_warm_start_at_solution_stops_at_first_check():
     b = prob.solve(tol=1e-6, x0=a["x"], y0=a["y"])
     assert b["info"]["status"] == oracle.pdhg.OPTIMAL and b["info"]["iters"] == 64
     prob.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replay_matches_direct_launches(precision):
+    """A run of eval_freq iterations replayed from a HIP graph (thousands of
+    replays, a host synchronisation and readback between replays) gives the
+    same bits as launching every kernel."""
+    lp = lpgen.config("c1", seed=3)
+    announce(f"graph vs direct c1 precision={precision}")
+    prob = problem(lp, precision=precision)
+    a = np_out(prob.solve(tol=1e-8, graphs=1))
+    b = np_out(prob.solve(tol=1e-8, graphs=0))
+    c = np_out(prob.solve(tol=1e-8, graphs=1))
+    for o in (b, c):
+        assert np.array_equal(a["x"], o["x"]) and np.array_equal(a["y"], o["y"]) and np.array_equal(a["r"], o["r"])
+        assert a["info"]["iters"] == o["info"]["iters"] and a["info"]["restarts"] == o["info"]["restarts"]
+    assert a["info"]["status"] == oracle.pdhg.OPTIMAL
+    prob.close()
+
+
+def test_graph_replay_c2_partial_run():
+    """max_iter not a multiple of eval_freq: graphs for the full runs, direct
+    launches for the last partial run; same bits as all-direct."""
+    lp = lpgen.config("c2", seed=2)
+    announce("graph vs direct c2 max_iter=3000")
+    prob = problem(lp)
+    a = np_out(prob.solve(max_iter=3000, graphs=1))
+    b = np_out(prob.solve(max_iter=3000, graphs=0))
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["y"], b["y"])
+    assert a["info"]["iters"] == b["info"]["iters"] == 3000
+    prob.close()
