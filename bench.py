@@ -8,10 +8,16 @@ values, 30% equality rows, 20% of the columns free above) to 1e-8 relative KKT
 error in FP64, inputs resident in HBM and the handle set up (transpose,
 rescaling, power iteration) before the timed region.  ``value`` is PDHG
 iterations per second over the timed steps.  The same run also reports the
-setup time, the FP32 + iterative-refinement solve of the same LP to 1e-8,
-the dominant kernel against the HBM roofline (HIP events on the library's
-stream), and the FP64 CPU oracle on a bounded sample of the same LP.
-Prints ONE JSON line.
+setup time, the FP32 + refinement solve of the same LP to 1e-8, the dominant
+kernel against the HBM roofline (HIP events on the library's stream), the
+HBM-bound skewed LP (m=2e6, n=5e6, Zipf row lengths, ~3e7 nonzeros) and the
+FP64 CPU oracle on a bounded sample of the medium LP.  Prints ONE JSON line.
+
+    python bench.py --kernels-only
+
+runs only the per-kernel timing of the medium LP and a 256 MiB copy of known
+size (used to calibrate hardware counters); it is the command profiled with
+rocprofv3 --pmc.
 """
 import os
 
@@ -21,7 +27,9 @@ for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
     os.environ[_v] = "1"
 
 import argparse
+import hashlib
 import json
+import re
 import sys
 import time
 
@@ -30,6 +38,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "c2"
+KERNEL_SOURCES = ("paper_2507_14051_amd/csrc/kernels_iter.hip", "paper_2507_14051_amd/csrc/device.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_primal_c2.md")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def algorithmic_bytes(m, n, nnz, fp=8):
@@ -44,6 +58,30 @@ def algorithmic_bytes(m, n, nnz, fp=8):
     return primal, dual
 
 
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per launch of the FP64 primal half-step from the committed
+    rocprofv3 --pmc summary, if it was taken on the current kernel sources."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,29 +89,44 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-hbm", action="store_true", help="skip the HBM-bound skewed LP")
     ap.add_argument("--profile-iters", type=int, default=400)
+    ap.add_argument("--kernels-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import lpgen
-    from paper_2507_14051_amd import FP64, MIXED, OPTIMAL, Problem
+    from paper_2507_14051_amd import MIXED, OPTIMAL, Problem
 
     dev = torch.device("cuda:0")
     lp = lpgen.config(WORKLOAD, seed=1)
     tol = lpgen.tolerance(WORKLOAD)
     m, n, nnz = lp.m, lp.n, lp.nnz
-    print(f"# workload {WORKLOAD}: m={m} n={n} nnz={nnz} max_row={lp.meta['max_row']}", file=sys.stderr, flush=True)
+    pb, db = algorithmic_bytes(m, n, nnz)
+    log(f"# workload {WORKLOAD}: m={m} n={n} nnz={nnz} max_row={lp.meta['max_row']}")
 
     t0 = time.perf_counter()
     prob = Problem(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, device=dev)
     torch.cuda.synchronize()
     setup_wall = time.perf_counter() - t0
     _, _, eta, power_iters = prob.scaling()
+
+    if args.kernels_only:
+        prof = prob.profile(iters=args.profile_iters)
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)   # 256 MiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"kernels_only": True, "primal_us": prof["primal_ms"] * 1e3,
+                          "dual_us": prof["dual_ms"] * 1e3, "iters": prof["iters"],
+                          "primal_bytes": pb, "dual_bytes": db, "copy_bytes": 2 * a.numel() * 8,
+                          "kernel_source_hash": kernel_source_hash()}), flush=True)
+        prob.close()
+        return
 
     for _ in range(args.warmup):
         prob.solve(tol=tol, want_r=False)
@@ -87,22 +140,24 @@ def main():
     iters = sum(i["iters"] for i in infos)
     ok = all(i["status"] == OPTIMAL for i in infos)
     ms_per_step = 1e3 * elapsed / args.steps
-    print(f"# fp64: {infos[-1]['iters']} iters, {ms_per_step:.1f} ms/solve, rel_kkt {infos[-1]['rel_kkt']:.2e}",
-          file=sys.stderr, flush=True)
+    log(f"# fp64: {infos[-1]['iters']} iters, {ms_per_step:.1f} ms/solve, rel_kkt {infos[-1]['rel_kkt']:.2e}")
 
-    # dominant kernel against the roofline: events around every launch
+    # dominant kernel against the roofline: HIP events around every launch
     prof = prob.profile(iters=args.profile_iters)
-    pb, db = algorithmic_bytes(m, n, nnz)
     kern = "primal" if prof["primal_ms"] >= prof["dual_ms"] else "dual"
     kms = prof["primal_ms"] if kern == "primal" else prof["dual_ms"]
     kbytes = pb if kern == "primal" else db
     achieved = kbytes / (kms * 1e-3) / 1e9
+    tr = load_traffic() if kern == "primal" else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_primal (transpose SpMV fused with the primal update), FP64",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": (tr["traffic_bytes_per_launch"] if tr else None),
+                "kernel": f"k_{kern} (fused {'transpose ' if kern == 'primal' else ''}SpMV + update), FP64",
                 "bytes_per_launch": kbytes, "avg_launch_us": round(kms * 1e3, 3),
+                "primal_avg_launch_us": round(prof["primal_ms"] * 1e3, 3),
                 "dual_avg_launch_us": round(prof["dual_ms"] * 1e3, 3),
-                "iter_us": round(prof["iter_ms"] * 1e3, 3)}
+                "iter_us_with_events": round(prof["iter_ms"] * 1e3, 3),
+                "solve_iter_us": round(1e6 * elapsed / iters, 3)}
     prob.close()
 
     mixed = None
@@ -115,39 +170,67 @@ def main():
         torch.cuda.synchronize()
         mt = (time.perf_counter() - t0) / args.steps
         profm = probm.profile(iters=args.profile_iters)
+        pb32, db32 = algorithmic_bytes(m, n, nnz, fp=4)
         mixed = {"time_to_tol_s": round(mt, 4), "iters": mi[-1]["iters"], "status": mi[-1]["status"],
                  "rel_kkt": mi[-1]["rel_kkt"], "iters_per_s": round(mi[-1]["iters"] / mt, 1),
                  "speedup_vs_fp64_time": round((elapsed / args.steps) / mt, 3),
-                 "primal_us": round(profm["primal_ms"] * 1e3, 3), "dual_us": round(profm["dual_ms"] * 1e3, 3)}
+                 "primal_us": round(profm["primal_ms"] * 1e3, 3), "dual_us": round(profm["dual_ms"] * 1e3, 3),
+                 "primal_gbs": round(pb32 / (profm["primal_ms"] * 1e-3) / 1e9, 1)}
         probm.close()
-        print(f"# mixed: {mixed}", file=sys.stderr, flush=True)
+        log(f"# mixed: {mixed}")
+
+    hbm = None
+    if not args.no_hbm:
+        lp3 = lpgen.config("c3b", seed=1)
+        m3, n3, nnz3 = lp3.m, lp3.n, lp3.nnz
+        log(f"# hbm-bound c3b: m={m3} n={n3} nnz={nnz3} max_row={lp3.meta['max_row']}")
+        t0 = time.perf_counter()
+        p3 = Problem(lp3.A, lp3.c, lp3.lc, lp3.uc, lp3.lv, lp3.uv, device=dev)
+        torch.cuda.synchronize()
+        s3 = time.perf_counter() - t0
+        del lp3
+        p3.solve(max_iter=64, tol=0.0, want_r=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        K3 = 640
+        p3.solve(max_iter=K3, tol=0.0, want_r=False)
+        torch.cuda.synchronize()
+        it_s = K3 / (time.perf_counter() - t0)
+        pr3 = p3.profile(iters=100)
+        pb3, db3 = algorithmic_bytes(m3, n3, nnz3)
+        hbm = {"workload": f"c3b: m={m3} n={n3} nnz={nnz3} Zipf(1.882) rows capped at 50,000, "
+                           f"values +-10^U[-3,3]", "setup_s": round(s3, 3), "iters_per_s": round(it_s, 1),
+               "primal_us": round(pr3["primal_ms"] * 1e3, 2), "dual_us": round(pr3["dual_ms"] * 1e3, 2),
+               "primal_gbs": round(pb3 / (pr3["primal_ms"] * 1e-3) / 1e9, 1),
+               "dual_gbs": round(db3 / (pr3["dual_ms"] * 1e-3) / 1e9, 1),
+               "iter_gbs": round((pb3 + db3) / (pr3["iter_ms"] * 1e-3) / 1e9, 1)}
+        hbm["iter_frac_of_peak"] = round(hbm["iter_gbs"] / HBM_PEAK_GBS, 4)
+        p3.close()
+        log(f"# hbm: {hbm}")
 
     cpu = None
     if not args.no_cpu:
         import oracle
         K = 60
-        t0 = time.perf_counter()
         res = oracle.solve(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv,
                            oracle.Params(tol=tol, max_iter=K, eta_override=eta))
-        cpu_iter_s = res.info["iter_s"]
-        cpu = {"value": round(K / cpu_iter_s, 3), "unit": "iter/s", "cores": 1, "kind": "oracle",
+        cpu = {"value": round(K / res.info["iter_s"], 3), "unit": "iter/s", "cores": 1, "kind": "oracle",
                "sample": f"{K} oracle iterations of the same LP (eta given; scaling {res.info['setup_s']:.1f}s "
                          f"excluded), NumPy/SciPy FP64 single thread; host nproc={os.cpu_count()}"}
-        print(f"# cpu: {cpu}", file=sys.stderr, flush=True)
+        log(f"# cpu: {cpu}")
 
-    value = iters / elapsed
     line = {
         "metric": "PDHG iterations/s, FP64 solve to 1e-8 relative KKT (time-to-tolerance and HBM roofline alongside)",
-        "value": round(value, 1), "unit": "iter/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "value": round(iters / elapsed, 1), "unit": "iter/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{WORKLOAD}: m={m} n={n} nnz={nnz} (8/row uniform columns, N(0,1) values, "
                                f"30% equality rows, 20% free columns), tol {tol:g}",
                    "seed": 1, "global_batch": 1, "parallelism": "single GPU"},
         "time_to_tol_s": round(elapsed / args.steps, 4), "iters_per_solve": infos[-1]["iters"],
         "restarts": infos[-1]["restarts"], "rel_kkt": infos[-1]["rel_kkt"], "all_optimal": ok,
         "setup_s": round(setup_wall, 4), "power_iters": power_iters,
-        "mixed": mixed, "roofline": roofline, "cpu_baseline": cpu,
+        "mixed": mixed, "hbm_bound": hbm, "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

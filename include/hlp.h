@@ -96,6 +96,10 @@ typedef struct {
   int32_t graphs;          /* 1: replay each run of eval_freq iterations (and its check)
                               from a captured HIP graph; 0: launch every kernel; 1.
                               Results are bitwise identical either way. */
+  int32_t stream_matrix;   /* [setup] -1: automatic; 1: load the matrix arrays in the
+                              half-steps as non-temporal (streaming) data; 0: cached.
+                              Automatic streams when both matrices exceed 128 MB.
+                              Results are bitwise identical either way; -1 */
 } hlp_params;
 
 /* Outcome of a solve.  Objectives and relative errors refer to the original
@@ -229,14 +233,15 @@ hlp_err hlp_unrolled_backward(hlp_lp* lp, const void* tape, size_t tape_bytes,
                               double* guc, double* glv, double* guv);
 
 /*
- * Measurement: run `iters` iterations of the hot loop from the current state
- * of a fresh zero start (no checks), recording a HIP event before and after
- * every kernel launch on the handle's stream, and write the mean duration in
- * milliseconds of each kernel kind to ms_out (host double[4]):
- *   [0] primal half-step (transpose SpMV fused with the primal update),
- *   [1] dual half-step (SpMV fused with the dual update),
- *   [2] total time per iteration,
- *   [3] iterations timed.
+ * Measurement: run `iters` iterations of the hot loop from a zero start (no
+ * checks, the two half-steps alternating as in a solve) on the handle's
+ * stream.  Each half-step is launched with a pair of HIP events that take the
+ * kernel's own start and end timestamps; ms_out (host double[4]) receives the
+ * mean duration in milliseconds of
+ *   [0] the primal half-step (transpose SpMV fused with the primal update),
+ *   [1] the dual half-step (SpMV fused with the dual update),
+ *   [2] one iteration, from two plain events around the whole run,
+ *   [3] the number of iterations timed.
  * precision selects the FP64 or the FP32 kernels (the handle must hold them).
  */
 hlp_err hlp_profile_iterations(hlp_lp* lp, const hlp_params* p, int32_t iters, double* ms_out);

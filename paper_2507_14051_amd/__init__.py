@@ -21,7 +21,8 @@ from .hlp import (FP64, MIXED, HLP_OK, ITER_LIMIT, NUMERICAL, OPTIMAL, STATUS_NA
 __all__ = ["Problem", "solve", "HlpError", "FP64", "MIXED", "OPTIMAL", "ITER_LIMIT", "TIME_LIMIT",
            "NUMERICAL", "STATUS_NAMES", "hlp_params_default"]
 
-SETUP_FIELDS = ("precision", "eta_override", "ruiz_iters", "pock_chambolle", "power_max_iter", "power_tol")
+SETUP_FIELDS = ("precision", "eta_override", "ruiz_iters", "pock_chambolle", "power_max_iter", "power_tol",
+                "stream_matrix")
 
 
 def _dev_tensor(a, dtype, device):

@@ -119,6 +119,8 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
   // row blocks and the step scalars
   L->rbA = c.take<int32_t>((int64_t)m + 2);
   L->rbT = c.take<int32_t>((int64_t)n + 2);
+  L->rbxA = c.take<int32_t>(4 * ((int64_t)m + 1));
+  L->rbxT = c.take<int32_t>(4 * ((int64_t)n + 1));
   L->rbtmp = c.take<int32_t>(2 * (N + 1));
   L->step = c.take<StepDev>(1);
   // reductions: 4 regions of partial_blocks x 8 doubles (at most one block per row)
@@ -182,6 +184,7 @@ hlp_err hlp_params_default(hlp_params* p) {
   p->trace_iters = 0;
   p->debug_poison_iter = 0;
   p->graphs = 1;
+  p->stream_matrix = -1;
   return HLP_OK;
 }
 
@@ -316,9 +319,9 @@ hlp_err hlp_lp_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr,
   lp->Lc = lanes_for(n ? (double)nnz / n : 1.0);
   if (hipError_t e = launch_transpose(lp); e != hipSuccess) return fail(hip_fail(e, "transpose"));
   // row blocks of A~ and A~^T for the hot SpMVs
-  if (hipError_t e = launch_build_row_blocks(lp, lp->rp, m, lp->rbA, lp->flags + 1); e != hipSuccess)
+  if (hipError_t e = launch_build_row_blocks(lp, lp->rp, m, lp->rbA, lp->rbxA, lp->flags + 1); e != hipSuccess)
     return fail(hip_fail(e, "row blocks"));
-  if (hipError_t e = launch_build_row_blocks(lp, lp->cp, n, lp->rbT, lp->flags + 2); e != hipSuccess)
+  if (hipError_t e = launch_build_row_blocks(lp, lp->cp, n, lp->rbT, lp->rbxT, lp->flags + 2); e != hipSuccess)
     return fail(hip_fail(e, "row blocks"));
   {
     int32_t cnt[3] = {0, 0, 0};
@@ -328,6 +331,7 @@ hlp_err hlp_lp_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr,
     lp->nbA = m ? cnt[1] : 0;
     lp->nbT = n ? cnt[2] : 0;
   }
+  lp->nt = p->stream_matrix > 0 || (p->stream_matrix < 0 && 2.0 * 12.0 * (double)nnz > 128e6);
   // 3. rescaling of A, then the vectors
   if (hipError_t e = launch_rescale(lp, p->ruiz_iters, p->pock_chambolle); e != hipSuccess)
     return fail(hip_fail(e, "rescale"));

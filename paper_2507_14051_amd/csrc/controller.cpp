@@ -341,28 +341,34 @@ hlp_err hlp_profile_iterations(hlp_lp* lp, const hlp_params* pp, int32_t iters, 
   }
   const double eta = lp->eta, om = p.omega0;
   HLP_HIP(launch_set_step(lp, eta / om, eta * om, p.gamma, 0, 1.0, 1.0));
-  std::vector<hipEvent_t> ev(2 * (size_t)iters + 1);
+  // Each half-step is launched with start/stop events that take the kernel's
+  // own begin and end timestamps; two plain events bracket the whole run.
+  std::vector<hipEvent_t> ev(4 * (size_t)iters + 2);
   for (auto& e : ev) HLP_HIP(hipEventCreate(&e));
-  HLP_HIP(hipEventRecord(ev[0], lp->stream));
+  hipEvent_t t_begin = ev[4 * (size_t)iters], t_end = ev[4 * (size_t)iters + 1];
+  HLP_HIP(hipEventRecord(t_begin, lp->stream));
   for (int32_t i = 0; i < iters; ++i) {
     StepArgs s;
     s.j = i;
+    s.ev_start = ev[4 * i];
+    s.ev_stop = ev[4 * i + 1];
     HLP_HIP(mixed ? launch_primal32(lp, s) : launch_primal(lp, s));
-    HLP_HIP(hipEventRecord(ev[2 * i + 1], lp->stream));
+    s.ev_start = ev[4 * i + 2];
+    s.ev_stop = ev[4 * i + 3];
     HLP_HIP(mixed ? launch_dual32(lp, s) : launch_dual(lp, s));
-    HLP_HIP(hipEventRecord(ev[2 * i + 2], lp->stream));
   }
+  HLP_HIP(hipEventRecord(t_end, lp->stream));
   HLP_HIP(hipStreamSynchronize(lp->stream));
   double tp = 0.0, td = 0.0;
   for (int32_t i = 0; i < iters; ++i) {
     float a = 0.f, b = 0.f;
-    HLP_HIP(hipEventElapsedTime(&a, ev[2 * i], ev[2 * i + 1]));
-    HLP_HIP(hipEventElapsedTime(&b, ev[2 * i + 1], ev[2 * i + 2]));
+    HLP_HIP(hipEventElapsedTime(&a, ev[4 * i], ev[4 * i + 1]));
+    HLP_HIP(hipEventElapsedTime(&b, ev[4 * i + 2], ev[4 * i + 3]));
     tp += a;
     td += b;
   }
   float all = 0.f;
-  HLP_HIP(hipEventElapsedTime(&all, ev[0], ev[2 * (size_t)iters]));
+  HLP_HIP(hipEventElapsedTime(&all, t_begin, t_end));
   for (auto& e : ev) (void)hipEventDestroy(e);
   ms_out[0] = tp / iters;
   ms_out[1] = td / iters;

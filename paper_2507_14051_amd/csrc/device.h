@@ -102,13 +102,52 @@ __device__ __forceinline__ T block_sum_to0(T v) {
 // row s + t (products staged in LDS, then summed left to right); in a
 // single-row block every thread returns that row's sum (strided partials, a
 // fixed shuffle tree and the waves in order).  Deterministic either way.
-template <typename ACC, typename V, typename X>
+// Each thread handles the nonzeros ps + tid + k*kBlock in batches of kRbUnroll:
+// all index and value loads of a batch are issued, then all gathers, then the
+// products, so a thread has a whole batch of gathers in flight instead of one.
+constexpr int kRbUnroll = 8;
+
+// NT: load the matrix arrays (idx, val) as streaming (non-temporal) data so a
+// matrix larger than the caches does not evict the gathered vector.
+template <bool NT, typename T>
+__device__ __forceinline__ T ld(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+template <typename ACC, bool NT = false, typename V, typename X>
 __device__ __forceinline__ ACC rb_dot(const int32_t* __restrict__ idx, const V* __restrict__ val,
                                       const X* __restrict__ vec, int ps, int pe, int a0, int a1,
                                       bool own, ACC* lds) {
   const int tid = threadIdx.x;
-  if (pe - ps <= kRbLds) {
-    for (int q = ps + tid; q < pe; q += kBlock) lds[q - ps] = (ACC)val[q] * (ACC)vec[idx[q]];
+  const bool staged = pe - ps <= kRbLds;
+  ACC part = 0;
+  for (int base = ps + tid; base < pe; base += kBlock * kRbUnroll) {
+    // Past the end, the clamped position repeats the last nonzero (a valid
+    // address, so the loads need no branch) and its product is dropped.
+    int ix[kRbUnroll];
+    V vv[kRbUnroll];
+#pragma unroll
+    for (int u = 0; u < kRbUnroll; ++u) {
+      const int q = min(base + u * kBlock, pe - 1);
+      ix[u] = ld<NT>(idx + q);
+      vv[u] = ld<NT>(val + q);
+    }
+    X g[kRbUnroll];
+#pragma unroll
+    for (int u = 0; u < kRbUnroll; ++u) g[u] = vec[ix[u]];
+#pragma unroll
+    for (int u = 0; u < kRbUnroll; ++u) {
+      const ACC prod = base + u * kBlock < pe ? (ACC)vv[u] * (ACC)g[u] : ACC(0);
+      if (staged) {
+        const int q = base + u * kBlock;
+        if (q < pe) lds[q - ps] = prod;
+      } else {
+        part += prod;
+      }
+    }
+  }
+  if (staged) {
     __syncthreads();
     ACC acc = 0;
     if (own)
@@ -116,8 +155,6 @@ __device__ __forceinline__ ACC rb_dot(const int32_t* __restrict__ idx, const V* 
     __syncthreads();
     return acc;
   }
-  ACC part = 0;
-  for (int q = ps + tid; q < pe; q += kBlock) part += (ACC)val[q] * (ACC)vec[idx[q]];
   return block_sum_to0(part);
 }
 

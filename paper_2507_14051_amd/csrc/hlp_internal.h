@@ -68,12 +68,19 @@ struct hlp_lp {
   int32_t *cp = nullptr, *row = nullptr;
   double* tval = nullptr;
   float* tval32 = nullptr;
-  double* val0 = nullptr;   // unscaled CSR values (kept to rescale after a vector update? no: for stats)
+  double* val0 = nullptr;   // unscaled CSR values (input of the scaling statistics)
   double* tval0 = nullptr;  // unscaled transpose values
   int32_t Lr = 8, Lc = 8;   // lanes per row for A~ and A~^T (setup and check-only kernels)
   // row blocks (see device.h) of A~ (rbA, nbA blocks) and of A~^T (rbT, nbT)
   int32_t *rbA = nullptr, *rbT = nullptr, *rbtmp = nullptr;
+  // the same blocks as {first row, end row, first nonzero, end nonzero}
+  // (int4 per block), so a half-step block needs a single table load
+  int32_t *rbxA = nullptr, *rbxT = nullptr;
   int32_t nbA = 0, nbT = 0;
+  // stream the matrix arrays with non-temporal loads (set when the two
+  // matrices exceed half of the 256 MB Infinity Cache, so they do not evict
+  // the gathered vectors)
+  bool nt = false;
   hlp::StepDev* step = nullptr;
   // captured runs of eval_freq iterations (see controller.cpp)
   void* graph_exec[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -159,8 +166,10 @@ struct StepArgs {
   int32_t residual = 0;      // compute the check quantities and write xhat / yhat
   uint8_t* mask_x = nullptr; // if set (FP64 only): write xhat and the clamp codes of v
   uint8_t* mask_y = nullptr; // if set (FP64 only): write yhat and the clamp codes of w
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // if set: timestamps of the kernel itself
 };
-hipError_t launch_build_row_blocks(hlp_lp* lp, const int32_t* ptr, int32_t rows, int32_t* rb, int32_t* count);
+hipError_t launch_build_row_blocks(hlp_lp* lp, const int32_t* ptr, int32_t rows, int32_t* rb, int32_t* rbx,
+                                   int32_t* count);
 hipError_t launch_set_step(hlp_lp* lp, double tau, double sigma, double gamma, int64_t k0, double P = 1.0,
                            double D = 1.0);
 hipError_t launch_primal(hlp_lp* lp, const StepArgs& s);

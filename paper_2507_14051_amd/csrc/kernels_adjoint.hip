@@ -57,39 +57,41 @@ __global__ void k_bwd_prep(PrepArgs p) {
 }
 
 struct ColArgs {
-  const int32_t* cp; const int32_t* row; const double* tval;
+  const int32_t* rb; const int32_t* cp; const int32_t* row; const double* tval;
   const double* gw; const double* dc; const double* Gx; const uint8_t* code;
   double* gxn; double* gxa; double* gct; double* glv; double* guv; double* u;
-  int32_t n; int32_t mode; double a, gamma, tau;
+  int32_t mode; double a, gamma, tau;
 };
 
-template <int L>
+// Transpose side over the row blocks of A~^T: xbar_bar = A~^T w_bar, then the
+// column epilogue.
 __global__ __launch_bounds__(kBlock) void k_bwd_cols(ColArgs p) {
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t j = t / L;
-  const int lane = threadIdx.x & (L - 1);
-  double acc = 0.0;
-  if (j < p.n) {
-    const int s = p.cp[j], e = p.cp[j + 1];
-    for (int q = s + lane; q < e; q += L) acc += p.tval[q] * p.gw[p.row[q]];
+  __shared__ double lds[kRbLds];
+  const int s = p.rb[blockIdx.x], e = p.rb[blockIdx.x + 1];
+  const int j = s + threadIdx.x;
+  const bool own = j < e;
+  int a0 = 0, a1 = 0;
+  double gn = 0.0, ga = 0.0;
+  uint8_t c = 0;
+  if (own) {
+    a0 = p.cp[j]; a1 = p.cp[j + 1];
+    gn = p.gxn[j]; ga = p.gxa[j]; c = p.code[j];
   }
-  acc = group_sum<L>(acc);
-  if (j >= p.n || lane != 0) return;
+  const double acc = rb_dot<double>(p.row, p.tval, p.gw, p.cp[s], p.cp[e], a0, a1, own, lds);
+  if (!own) return;
   double gxh, gin = 0.0;
   if (p.mode == MODE_LAST) {
     gxh = p.Gx ? p.dc[j] * p.Gx[j] : 0.0;
   } else if (p.mode == MODE_RESTART) {
-    gxh = p.gxn[j] + p.gxa[j];
+    gxh = gn + ga;
     p.gxa[j] = 0.0;
   } else {
-    const double g = p.gxn[j];
-    gxh = p.a * (1.0 + p.gamma) * g;
-    gin = -p.a * p.gamma * g;
-    p.gxa[j] += (1.0 - p.a) * g;
+    gxh = p.a * (1.0 + p.gamma) * gn;
+    gin = -p.a * p.gamma * gn;
+    p.gxa[j] = ga + (1.0 - p.a) * gn;
   }
   gxh = gxh + 2.0 * acc;
   gin -= acc;
-  const uint8_t c = p.code[j];
   if (c == 1) p.glv[j] += gxh;
   if (c == 2) p.guv[j] += gxh;
   const double gv = c == 0 ? gxh : 0.0;
@@ -100,25 +102,27 @@ __global__ __launch_bounds__(kBlock) void k_bwd_cols(ColArgs p) {
 }
 
 struct RowArgs {
-  const int32_t* rp; const int32_t* col; const double* val; const double* u;
+  const int32_t* rb; const int32_t* rp; const int32_t* col; const double* val; const double* u;
   PrepArgs prev;
   int32_t do_prev;
 };
 
-template <int L>
+// Matrix side over the row blocks of A~: y_bar = (prep part) + A~ u, fused
+// with the row preparation of the previous iteration.
 __global__ __launch_bounds__(kBlock) void k_bwd_rows(RowArgs p) {
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t i = t / L;
-  const int lane = threadIdx.x & (L - 1);
-  const int32_t m = p.prev.m;
-  double acc = 0.0;
-  if (i < m) {
-    const int s = p.rp[i], e = p.rp[i + 1];
-    for (int q = s + lane; q < e; q += L) acc += p.val[q] * p.u[p.col[q]];
+  __shared__ double lds[kRbLds];
+  const int s = p.rb[blockIdx.x], e = p.rb[blockIdx.x + 1];
+  const int i = s + threadIdx.x;
+  const bool own = i < e;
+  int a0 = 0, a1 = 0;
+  double pyi = 0.0;
+  if (own) {
+    a0 = p.rp[i]; a1 = p.rp[i + 1];
+    pyi = p.prev.py[i];
   }
-  acc = group_sum<L>(acc);
-  if (i >= m || lane != 0) return;
-  const double gyin = p.prev.py[i] + acc;
+  const double acc = rb_dot<double>(p.col, p.val, p.u, p.rp[s], p.rp[e], a0, a1, own, lds);
+  if (!own) return;
+  const double gyin = pyi + acc;
   p.prev.gyn[i] = gyin;
   if (p.do_prev) prep_row(p.prev, i, gyin);
 }
@@ -148,34 +152,6 @@ __global__ void k_zero_adj(AdjVecs v, int32_t n, int32_t m) {
   }
 }
 
-template <int L>
-struct ColsL {
-  static hipError_t run(const ColArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_bwd_cols<L>), dim3(nb), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
-  }
-};
-template <int L>
-struct RowsL {
-  static hipError_t run(const RowArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_bwd_rows<L>), dim3(nb), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
-  }
-};
-
-template <template <int> class F, typename... Args>
-hipError_t dispatch_L(int L, Args... args) {
-  switch (L) {
-    case 1: return F<1>::run(args...);
-    case 2: return F<2>::run(args...);
-    case 4: return F<4>::run(args...);
-    case 8: return F<8>::run(args...);
-    case 16: return F<16>::run(args...);
-    case 32: return F<32>::run(args...);
-    default: return F<64>::run(args...);
-  }
-}
-
 PrepArgs prep_args(hlp_lp* lp, const AdjVecs& v, const AdjIter& it, const uint8_t* my, const double* Gy) {
   return PrepArgs{lp->dr, Gy, my, v.gyn, v.gya, v.glc, v.guc, v.gw, v.py, lp->m, it.mode, it.a, it.gamma,
                   it.sigma};
@@ -191,16 +167,20 @@ hipError_t launch_bwd_prep(hlp_lp* lp, const AdjVecs& v, const AdjIter& it, cons
 
 hipError_t launch_bwd_cols(hlp_lp* lp, const AdjVecs& v, const AdjIter& it, const uint8_t* mx, const double* Gx) {
   if (lp->n == 0) return hipSuccess;
-  ColArgs a{lp->cp, lp->row, lp->tval, v.gw, lp->dc, Gx, mx, v.gxn, v.gxa, v.gct, v.glv, v.guv, v.u,
-            lp->n, it.mode, it.a, it.gamma, it.tau};
-  return dispatch_L<ColsL>(lp->Lc, a, nblocks((int64_t)lp->n * lp->Lc), lp->stream);
+  ColArgs a{lp->rbT, lp->cp, lp->row, lp->tval, v.gw, lp->dc, Gx, mx, v.gxn, v.gxa, v.gct, v.glv, v.guv, v.u,
+            it.mode, it.a, it.gamma, it.tau};
+  if (lp->nbT == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bwd_cols, dim3(lp->nbT), dim3(kBlock), 0, lp->stream, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_bwd_rows(hlp_lp* lp, const AdjVecs& v, int32_t do_prev, const AdjIter& prev,
                            const uint8_t* my_prev, const double* Gy) {
   if (lp->m == 0) return hipSuccess;
-  RowArgs a{lp->rp, lp->col, lp->val, v.u, prep_args(lp, v, prev, my_prev, Gy), do_prev};
-  return dispatch_L<RowsL>(lp->Lr, a, nblocks((int64_t)lp->m * lp->Lr), lp->stream);
+  RowArgs a{lp->rbA, lp->rp, lp->col, lp->val, v.u, prep_args(lp, v, prev, my_prev, Gy), do_prev};
+  if (lp->nbA == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bwd_rows, dim3(lp->nbA), dim3(kBlock), 0, lp->stream, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_bwd_out(hlp_lp* lp, const AdjVecs& v, double* gc, double* glc, double* guc, double* glv,

@@ -12,6 +12,8 @@
 // Sec. 2.2, the PID distances, the row side of the KKT error of Sec. 4).  A
 // transpose kernel adds the column side of the KKT error.  All reductions are
 // per-block partials summed in block order: results are bit-reproducible.
+#include <hip/hip_ext.h>
+
 #include <cmath>
 
 #include "device.h"
@@ -48,7 +50,7 @@ __device__ __forceinline__ double halpern_a(const StepDev* s, int32_t j) {
 
 // ============================================================================ FP64 half-steps
 struct PrimalArgs {
-  const int32_t* rb; const int32_t* cp; const int32_t* row; const double* tval;
+  const int4* rb; const int32_t* cp; const int32_t* row; const double* tval;
   const double* y; double* x; const double* xa; const double* ct; const double* lv; const double* uv;
   double* xbar; double* xh; double* dx; double* partials; uint8_t* mask; const StepDev* step;
   int32_t j;
@@ -56,11 +58,13 @@ struct PrimalArgs {
 
 // MODE 0: plain step; 1: also xhat, x - xhat and the check partials;
 // 2: also xhat and the clamp code of v (for the reverse mode).
-template <int MODE>
+// NT: stream the matrix arrays (large matrices, see hlp_lp::nt).
+template <int MODE, bool NT>
 __global__ __launch_bounds__(kBlock) void k_primal(PrimalArgs p) {
   constexpr bool RES = MODE == 1;
   __shared__ double lds[kRbLds];
-  const int s = p.rb[blockIdx.x], e = p.rb[blockIdx.x + 1];
+  const int4 blk = p.rb[blockIdx.x];
+  const int s = blk.x, e = blk.y, ps = blk.z, pe = blk.w;
   const int j = s + threadIdx.x;
   const bool own = j < e;
   double xj = 0.0, cj = 0.0, lo = 0.0, hi = 0.0, xaj = 0.0;
@@ -69,8 +73,7 @@ __global__ __launch_bounds__(kBlock) void k_primal(PrimalArgs p) {
     xj = p.x[j]; cj = p.ct[j]; lo = p.lv[j]; hi = p.uv[j]; xaj = p.xa[j];
     a0 = p.cp[j]; a1 = p.cp[j + 1];
   }
-  const int ps = p.cp[s], pe = p.cp[e];
-  const double g = rb_dot<double>(p.row, p.tval, p.y, ps, pe, a0, a1, own, lds);
+  const double g = rb_dot<double, NT>(p.row, p.tval, p.y, ps, pe, a0, a1, own, lds);
   double q0 = 0.0, q1 = 0.0;
   if (own) {
     const double tau = p.step->tau, gam = p.step->gamma, a = halpern_a(p.step, p.j);
@@ -98,19 +101,20 @@ __global__ __launch_bounds__(kBlock) void k_primal(PrimalArgs p) {
 }
 
 struct DualArgs {
-  const int32_t* rb; const int32_t* rp; const int32_t* col; const double* val;
+  const int4* rb; const int32_t* rp; const int32_t* col; const double* val;
   const double* xbar; const double* dx; const double* xh;
   double* y; const double* ya; const double* lc; const double* uc; const double* dr;
   double* yh; double* partials; uint8_t* mask; const StepDev* step;
   int32_t j;
 };
 
-// MODE as for k_primal (the code is that of w against the row bounds).
-template <int MODE>
+// MODE and NT as for k_primal (the code is that of w against the row bounds).
+template <int MODE, bool NT>
 __global__ __launch_bounds__(kBlock) void k_dual(DualArgs p) {
   constexpr bool RES = MODE == 1;
   __shared__ double lds[kRbLds];
-  const int s = p.rb[blockIdx.x], e = p.rb[blockIdx.x + 1];
+  const int4 blk = p.rb[blockIdx.x];
+  const int s = blk.x, e = blk.y, ps = blk.z, pe = blk.w;
   const int i = s + threadIdx.x;
   const bool own = i < e;
   double yi = 0.0, lo = 0.0, hi = 0.0, yai = 0.0, dri = 1.0;
@@ -120,8 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_dual(DualArgs p) {
     if (RES) dri = p.dr[i];
     a0 = p.rp[i]; a1 = p.rp[i + 1];
   }
-  const int ps = p.rp[s], pe = p.rp[e];
-  const double h = rb_dot<double>(p.col, p.val, p.xbar, ps, pe, a0, a1, own, lds);
+  const double h = rb_dot<double, NT>(p.col, p.val, p.xbar, ps, pe, a0, a1, own, lds);
   double adx = 0.0, axh = 0.0;
   if (RES) {
     adx = rb_dot<double>(p.col, p.val, p.dx, ps, pe, a0, a1, own, lds);
@@ -241,16 +244,17 @@ __global__ __launch_bounds__(kBlock) void k_kkt_rows(KktRowArgs p) {
 // (c', lv', uv', lc', uc', b):  yhat' = y' + sigma'(clamp(h - (b + y')/sigma') - h).
 // Products and sums in FP32; the check partials accumulate in FP64.
 struct Primal32Args {
-  const int32_t* rb; const int32_t* cp; const int32_t* row; const float* tval;
+  const int4* rb; const int32_t* cp; const int32_t* row; const float* tval;
   const float* y; float* x; const float* xa; const float* c; const float* lv; const float* uv;
   float* xbar; float* xh; float* dx; double* partials; const StepDev* step;
   int32_t j;
 };
 
-template <bool RES>
+template <bool RES, bool NT>
 __global__ __launch_bounds__(kBlock) void k_primal32(Primal32Args p) {
   __shared__ float lds[kRbLds];
-  const int s = p.rb[blockIdx.x], e = p.rb[blockIdx.x + 1];
+  const int4 blk = p.rb[blockIdx.x];
+  const int s = blk.x, e = blk.y, ps = blk.z, pe = blk.w;
   const int j = s + threadIdx.x;
   const bool own = j < e;
   float xj = 0.0f, cj = 0.0f, lo = 0.0f, hi = 0.0f, xaj = 0.0f;
@@ -259,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_primal32(Primal32Args p) {
     xj = p.x[j]; cj = p.c[j]; lo = p.lv[j]; hi = p.uv[j]; xaj = p.xa[j];
     a0 = p.cp[j]; a1 = p.cp[j + 1];
   }
-  const float g = rb_dot<float>(p.row, p.tval, p.y, p.cp[s], p.cp[e], a0, a1, own, lds);
+  const float g = rb_dot<float, NT>(p.row, p.tval, p.y, ps, pe, a0, a1, own, lds);
   double q0 = 0.0, q1 = 0.0;
   if (own) {
     const float tau = (float)p.step->tau, gam = (float)p.step->gamma, a = (float)halpern_a(p.step, p.j);
@@ -283,17 +287,18 @@ __global__ __launch_bounds__(kBlock) void k_primal32(Primal32Args p) {
 }
 
 struct Dual32Args {
-  const int32_t* rb; const int32_t* rp; const int32_t* col; const float* val;
+  const int4* rb; const int32_t* rp; const int32_t* col; const float* val;
   const float* xbar; const float* dx;
   float* y; const float* ya; const float* lc; const float* uc; const float* b;
   float* yh; double* partials; const StepDev* step;
   int32_t j;
 };
 
-template <bool RES>
+template <bool RES, bool NT>
 __global__ __launch_bounds__(kBlock) void k_dual32(Dual32Args p) {
   __shared__ double lds[kRbLds];
-  const int s = p.rb[blockIdx.x], e = p.rb[blockIdx.x + 1];
+  const int4 blk = p.rb[blockIdx.x];
+  const int s = blk.x, e = blk.y, ps = blk.z, pe = blk.w;
   const int i = s + threadIdx.x;
   const bool own = i < e;
   float yi = 0.0f, lo = 0.0f, hi = 0.0f, yai = 0.0f, bi = 0.0f;
@@ -302,8 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_dual32(Dual32Args p) {
     yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i]; bi = p.b[i];
     a0 = p.rp[i]; a1 = p.rp[i + 1];
   }
-  const int ps = p.rp[s], pe = p.rp[e];
-  const float h = rb_dot<float>(p.col, p.val, p.xbar, ps, pe, a0, a1, own, reinterpret_cast<float*>(lds));
+  const float h = rb_dot<float, NT>(p.col, p.val, p.xbar, ps, pe, a0, a1, own, reinterpret_cast<float*>(lds));
   double adx = 0.0;
   if (RES) adx = rb_dot<double>(p.col, p.val, p.dx, ps, pe, a0, a1, own, lds);
   double q[3] = {0.0, 0.0, 0.0};
@@ -473,6 +477,17 @@ Region make_region(const double* p, int64_t nb, std::initializer_list<int> qs, u
   return r;
 }
 
+// A half-step launch; with events in s, they take the kernel's own start and
+// end timestamps (for the per-kernel timing of hlp_profile_iterations).
+template <typename K, typename A>
+hipError_t launch_step_kernel(K kernel, int32_t nblk, const StepArgs& s, hipStream_t st, const A& a) {
+  if (s.ev_start)
+    hipExtLaunchKernelGGL(kernel, dim3(nblk), dim3(kBlock), 0, st, s.ev_start, s.ev_stop, 0, a);
+  else
+    hipLaunchKernelGGL(kernel, dim3(nblk), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 // ============================================================================ launchers
@@ -483,24 +498,22 @@ hipError_t launch_set_step(hlp_lp* lp, double tau, double sigma, double gamma, i
 
 hipError_t launch_primal(hlp_lp* lp, const StepArgs& s) {
   if (lp->nbT == 0) return hipSuccess;
-  PrimalArgs a{lp->rbT, lp->cp, lp->row, lp->tval, lp->y, lp->x, lp->xa, lp->ct, lp->lvt, lp->uvt,
+  PrimalArgs a{reinterpret_cast<const int4*>(lp->rbxT), lp->cp, lp->row, lp->tval, lp->y, lp->x, lp->xa, lp->ct, lp->lvt, lp->uvt,
                lp->xbar, lp->xh, lp->dxv, region(lp, R_PRIMAL), s.mask_x, lp->step, s.j};
-  const dim3 g(lp->nbT), b(kBlock);
-  if (s.mask_x) hipLaunchKernelGGL(k_primal<2>, g, b, 0, lp->stream, a);
-  else if (s.residual) hipLaunchKernelGGL(k_primal<1>, g, b, 0, lp->stream, a);
-  else hipLaunchKernelGGL(k_primal<0>, g, b, 0, lp->stream, a);
-  return hipGetLastError();
+  if (s.mask_x) return launch_step_kernel(k_primal<2, false>, lp->nbT, s, lp->stream, a);
+  if (s.residual) return launch_step_kernel(k_primal<1, false>, lp->nbT, s, lp->stream, a);
+  if (lp->nt) return launch_step_kernel(k_primal<0, true>, lp->nbT, s, lp->stream, a);
+  return launch_step_kernel(k_primal<0, false>, lp->nbT, s, lp->stream, a);
 }
 
 hipError_t launch_dual(hlp_lp* lp, const StepArgs& s) {
   if (lp->nbA == 0) return hipSuccess;
-  DualArgs a{lp->rbA, lp->rp, lp->col, lp->val, lp->xbar, lp->dxv, lp->xh, lp->y, lp->ya, lp->lct, lp->uct,
+  DualArgs a{reinterpret_cast<const int4*>(lp->rbxA), lp->rp, lp->col, lp->val, lp->xbar, lp->dxv, lp->xh, lp->y, lp->ya, lp->lct, lp->uct,
              lp->dr, lp->yh, region(lp, R_DUAL), s.mask_y, lp->step, s.j};
-  const dim3 g(lp->nbA), b(kBlock);
-  if (s.mask_y) hipLaunchKernelGGL(k_dual<2>, g, b, 0, lp->stream, a);
-  else if (s.residual) hipLaunchKernelGGL(k_dual<1>, g, b, 0, lp->stream, a);
-  else hipLaunchKernelGGL(k_dual<0>, g, b, 0, lp->stream, a);
-  return hipGetLastError();
+  if (s.mask_y) return launch_step_kernel(k_dual<2, false>, lp->nbA, s, lp->stream, a);
+  if (s.residual) return launch_step_kernel(k_dual<1, false>, lp->nbA, s, lp->stream, a);
+  if (lp->nt) return launch_step_kernel(k_dual<0, true>, lp->nbA, s, lp->stream, a);
+  return launch_step_kernel(k_dual<0, false>, lp->nbA, s, lp->stream, a);
 }
 
 hipError_t launch_kkt_cols(hlp_lp* lp, double* r_out) {
@@ -592,20 +605,20 @@ hipError_t launch_poison(hlp_lp* lp) {
 
 hipError_t launch_primal32(hlp_lp* lp, const StepArgs& s) {
   if (lp->nbT == 0) return hipSuccess;
-  Primal32Args a{lp->rbT, lp->cp, lp->row, lp->tval32, lp->y32, lp->x32, lp->xa32, lp->c32, lp->lv32, lp->uv32,
+  Primal32Args a{reinterpret_cast<const int4*>(lp->rbxT), lp->cp, lp->row, lp->tval32, lp->y32, lp->x32, lp->xa32, lp->c32, lp->lv32, lp->uv32,
                  lp->xbar32, lp->xh32, lp->dx32, region(lp, R_PRIMAL), lp->step, s.j};
-  if (s.residual) hipLaunchKernelGGL(k_primal32<true>, dim3(lp->nbT), dim3(kBlock), 0, lp->stream, a);
-  else hipLaunchKernelGGL(k_primal32<false>, dim3(lp->nbT), dim3(kBlock), 0, lp->stream, a);
-  return hipGetLastError();
+  if (s.residual) return launch_step_kernel(k_primal32<true, false>, lp->nbT, s, lp->stream, a);
+  if (lp->nt) return launch_step_kernel(k_primal32<false, true>, lp->nbT, s, lp->stream, a);
+  return launch_step_kernel(k_primal32<false, false>, lp->nbT, s, lp->stream, a);
 }
 
 hipError_t launch_dual32(hlp_lp* lp, const StepArgs& s) {
   if (lp->nbA == 0) return hipSuccess;
-  Dual32Args a{lp->rbA, lp->rp, lp->col, lp->val32, lp->xbar32, lp->dx32, lp->y32, lp->ya32, lp->lc32, lp->uc32,
+  Dual32Args a{reinterpret_cast<const int4*>(lp->rbxA), lp->rp, lp->col, lp->val32, lp->xbar32, lp->dx32, lp->y32, lp->ya32, lp->lc32, lp->uc32,
                lp->b32, lp->yh32, region(lp, R_DUAL), lp->step, s.j};
-  if (s.residual) hipLaunchKernelGGL(k_dual32<true>, dim3(lp->nbA), dim3(kBlock), 0, lp->stream, a);
-  else hipLaunchKernelGGL(k_dual32<false>, dim3(lp->nbA), dim3(kBlock), 0, lp->stream, a);
-  return hipGetLastError();
+  if (s.residual) return launch_step_kernel(k_dual32<true, false>, lp->nbA, s, lp->stream, a);
+  if (lp->nt) return launch_step_kernel(k_dual32<false, true>, lp->nbA, s, lp->stream, a);
+  return launch_step_kernel(k_dual32<false, false>, lp->nbA, s, lp->stream, a);
 }
 
 hipError_t launch_combine(hlp_lp* lp) {

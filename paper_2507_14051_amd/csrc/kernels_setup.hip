@@ -282,6 +282,18 @@ __global__ void k_rb_scatter(const int32_t* __restrict__ flags, const int32_t* _
   }
 }
 
+// rbx[4b..4b+3] = {first row, end row, first nonzero, end nonzero} of block b.
+__global__ void k_rb_expand(const int32_t* __restrict__ rb, const int32_t* __restrict__ ptr, int32_t rows,
+                            const int32_t* __restrict__ count, int32_t* __restrict__ rbx) {
+  int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (b >= rows || b >= *count) return;
+  const int s = rb[b], e = rb[b + 1];
+  rbx[4 * b] = s;
+  rbx[4 * b + 1] = e;
+  rbx[4 * b + 2] = ptr[s];
+  rbx[4 * b + 3] = ptr[e];
+}
+
 // ----------------------------------------------------------------- rescaling
 // Per-row statistic of |d_r[i] a_ij d_c[j]| over a CSR (MAX or SUM), then
 // rho = sqrt(stat) (1 for an empty row).  Used for both A (rows) and A^T
@@ -368,26 +380,30 @@ __global__ void k_scale_vectors(const double* __restrict__ c, const double* __re
 }
 
 // ----------------------------------------------------------------- power iteration
-template <int L>
-__global__ __launch_bounds__(kBlock) void k_spmv_plain(const int32_t* __restrict__ ptr,
+// out = A~ x over row blocks; with partials, per-block sums of out^2.
+__global__ __launch_bounds__(kBlock) void k_spmv_plain(const int32_t* __restrict__ rb,
+                                                       const int32_t* __restrict__ ptr,
                                                        const int32_t* __restrict__ idx,
                                                        const double* __restrict__ val,
-                                                       const double* __restrict__ x, int32_t rows,
+                                                       const double* __restrict__ x,
                                                        double* __restrict__ out,
                                                        const PowerState* __restrict__ ps,
                                                        double* __restrict__ partials) {
   if (ps->done) return;
-  int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  int64_t i = t / L;
-  int lane = threadIdx.x & (L - 1);
-  double s = 0.0;
-  if (i < rows)
-    for (int p = ptr[i] + lane; p < ptr[i + 1]; p += L) s += val[p] * x[idx[p]];
-  s = group_sum<L>(s);
+  __shared__ double lds[kRbLds];
+  const int s = rb[blockIdx.x], e = rb[blockIdx.x + 1];
+  const int i = s + threadIdx.x;
+  const bool own = i < e;
+  int a0 = 0, a1 = 0;
+  if (own) {
+    a0 = ptr[i];
+    a1 = ptr[i + 1];
+  }
+  const double v = rb_dot<double>(idx, val, x, ptr[s], ptr[e], a0, a1, own, lds);
   double q[1] = {0.0};
-  if (i < rows && lane == 0) {
-    out[i] = s;
-    q[0] = s * s;
+  if (own) {
+    out[i] = v;
+    q[0] = v * v;
   }
   if (partials) block_reduce_store<1>(q, partials + blockIdx.x);
 }
@@ -495,17 +511,6 @@ struct ApplyScaling {
     return hipGetLastError();
   }
 };
-template <int L>
-struct SpmvPlain {
-  static hipError_t run(const int32_t* ptr, const int32_t* idx, const double* val, const double* x,
-                        int32_t rows, double* out, const PowerState* ps, double* partials,
-                        hipStream_t s) {
-    hipLaunchKernelGGL((k_spmv_plain<L>), dim3(nblocks((int64_t)rows * L)), dim3(kBlock), 0, s, ptr,
-                       idx, val, x, rows, out, ps, partials);
-    return hipGetLastError();
-  }
-};
-
 hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t N, int32_t* tmp, hipStream_t s) {
   if (N <= 0) return hipSuccess;
   int64_t NB = (N + kScanTile - 1) / kScanTile;
@@ -598,7 +603,8 @@ hipError_t launch_transpose(hlp_lp* lp) {
   return hipGetLastError();
 }
 
-hipError_t launch_build_row_blocks(hlp_lp* lp, const int32_t* ptr, int32_t rows, int32_t* rb, int32_t* count) {
+hipError_t launch_build_row_blocks(hlp_lp* lp, const int32_t* ptr, int32_t rows, int32_t* rb, int32_t* rbx,
+                                   int32_t* count) {
   if (rows == 0) return hipSuccess;
   hipStream_t s = lp->stream;
   int32_t* flags = lp->rbtmp;
@@ -608,6 +614,8 @@ hipError_t launch_build_row_blocks(hlp_lp* lp, const int32_t* ptr, int32_t rows,
   if (e != hipSuccess) return e;
   if ((e = scan_exclusive(flags, pos, rows, lp->scan_tmp, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_rb_scatter, dim3(nblocks(rows)), dim3(kBlock), 0, s, flags, pos, rows, rb, count);
+  hipLaunchKernelGGL(k_rb_expand, dim3(nblocks(rows)), dim3(kBlock), 0, s, rb, ptr, rows, (const int32_t*)count,
+                     rbx);
   return hipGetLastError();
 }
 
@@ -669,14 +677,13 @@ hipError_t launch_power(hlp_lp* lp, int32_t passes, int32_t first_pass, int32_t 
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_fill(lp->pv, 1.0 / std::sqrt((double)n), n, s)) != hipSuccess) return e;
   }
-  const int64_t nbc = nblocks((int64_t)n * lp->Lc);
+  const int64_t nbc = lp->nbT;
   for (int k = 0; k < passes; ++k) {
-    e = dispatch_L<SpmvPlain>(lp->Lr, lp->rp, lp->col, lp->val, lp->pv, m, lp->pu,
-                              (const PowerState*)lp->pstate, (double*)nullptr, s);
-    if (e != hipSuccess) return e;
-    e = dispatch_L<SpmvPlain>(lp->Lc, lp->cp, lp->row, lp->tval, lp->pu, n, lp->pw,
-                              (const PowerState*)lp->pstate, lp->partials, s);
-    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_spmv_plain, dim3(lp->nbA), dim3(kBlock), 0, s, lp->rbA, lp->rp, lp->col, lp->val, lp->pv,
+                       lp->pu, (const PowerState*)lp->pstate, (double*)nullptr);
+    hipLaunchKernelGGL(k_spmv_plain, dim3(lp->nbT), dim3(kBlock), 0, s, lp->rbT, lp->cp, lp->row, lp->tval, lp->pu,
+                       lp->pw, (const PowerState*)lp->pstate, lp->partials);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_power_finish, dim3(1), dim3(kBlock), 0, s, lp->partials, nbc, lp->pstate,
                        max_iter, tol);
     hipLaunchKernelGGL(k_power_normalize, dim3(nblocks(n)), dim3(kBlock), 0, s, lp->pw, lp->pv, n,

@@ -33,6 +33,7 @@ class HlpParams(C.Structure):
         ("ruiz_iters", C.c_int32), ("pock_chambolle", C.c_int32), ("power_max_iter", C.c_int32),
         ("restart_to_current", C.c_int32), ("power_tol", C.c_double), ("pid_min_norm", C.c_double),
         ("trace_iters", C.c_int32), ("debug_poison_iter", C.c_int32), ("graphs", C.c_int32),
+        ("stream_matrix", C.c_int32),
     ]
 
 

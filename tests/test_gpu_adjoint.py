@@ -57,6 +57,27 @@ def test_gradients_match_oracle(seed):
     prob.close()
 
 
+def test_gradients_long_rows_match_oracle():
+    """Rows longer than the LDS stage take the block-wide reduction path in the
+    reverse kernels too."""
+    lp = lpgen.gen(1500, 12000, zipf_alpha=1.3, cap=6000, eq_frac=0.3, free_frac=0.2, values="normal", seed=9)
+    assert (np.diff(lp.A.indptr) > 4096).sum() > 10
+    K, ckpt = 120, 25
+    announce(f"adjoint long rows nnz={lp.nnz} K={K}")
+    prob = problem(lp)
+    _, _, eta, _ = prob.scaling()
+    rng = np.random.default_rng(5)
+    gx = rng.standard_normal(lp.n); gy = rng.standard_normal(lp.m)
+    x, y, g = _grads(prob, lp, K, ckpt, gx, gy, eval_freq=16)
+    p = Params(eval_freq=16)
+    fw = unrolled_forward(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, p, K, eta=eta)
+    assert rel(x, fw["x"]) <= 1e-10 and rel(y, fw["y"]) <= 1e-10
+    go = unrolled_vjp(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, p, K, fw["schedule"], eta, gx, gy)
+    for key in KEYS:
+        assert rel(g[key], go[key]) <= 1e-9, (key, rel(g[key], go[key]))
+    prob.close()
+
+
 def test_checkpoint_interval_does_not_change_gradients():
     lp = lpgen.config("c5", seed=3, scale=0.01)
     K = 120
