@@ -82,6 +82,44 @@ def load_traffic():
     return d
 
 
+def measure_hbm(dev):
+    """Iteration rate and per-kernel GB/s on the large skewed LP (rows of
+    Zipf-distributed length), whose two matrices exceed the 256 MB Infinity
+    Cache: the HBM-bound case."""
+    import torch
+
+    import lpgen
+    from paper_2507_14051_amd import Problem
+
+    lp3 = lpgen.config("c3b", seed=1)
+    m3, n3, nnz3 = lp3.m, lp3.n, lp3.nnz
+    log(f"# hbm-bound c3b: m={m3} n={n3} nnz={nnz3} max_row={lp3.meta['max_row']}")
+    t0 = time.perf_counter()
+    p3 = Problem(lp3.A, lp3.c, lp3.lc, lp3.uc, lp3.lv, lp3.uv, device=dev)
+    torch.cuda.synchronize()
+    s3 = time.perf_counter() - t0
+    del lp3
+    p3.solve(max_iter=64, tol=0.0, want_r=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    K3 = 640
+    p3.solve(max_iter=K3, tol=0.0, want_r=False)
+    torch.cuda.synchronize()
+    it_s = K3 / (time.perf_counter() - t0)
+    pr3 = p3.profile(iters=100)
+    pb3, db3 = algorithmic_bytes(m3, n3, nnz3)
+    hbm = {"workload": f"c3b: m={m3} n={n3} nnz={nnz3} Zipf(1.882) rows capped at 50,000, "
+                       f"values +-10^U[-3,3]", "setup_s": round(s3, 3), "iters_per_s": round(it_s, 1),
+           "primal_us": round(pr3["primal_ms"] * 1e3, 2), "dual_us": round(pr3["dual_ms"] * 1e3, 2),
+           "primal_gbs": round(pb3 / (pr3["primal_ms"] * 1e-3) / 1e9, 1),
+           "dual_gbs": round(db3 / (pr3["dual_ms"] * 1e-3) / 1e9, 1),
+           "iter_gbs": round((pb3 + db3) / (pr3["iter_ms"] * 1e-3) / 1e9, 1)}
+    hbm["iter_frac_of_peak"] = round(hbm["iter_gbs"] / HBM_PEAK_GBS, 4)
+    p3.close()
+    log(f"# hbm: {hbm}")
+    return hbm
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,7 +129,10 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-hbm", action="store_true", help="skip the HBM-bound skewed LP")
     ap.add_argument("--profile-iters", type=int, default=400)
-    ap.add_argument("--kernels-only", action="store_true")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only time the half-steps of --kernels-workload and a 256 MiB copy (for counter runs)")
+    ap.add_argument("--kernels-workload", default=WORKLOAD, choices=("c2", "c3b"))
+    ap.add_argument("--hbm-only", action="store_true", help="only the skewed-LP measurement (for profiling it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -103,11 +144,15 @@ def main():
     from paper_2507_14051_amd import MIXED, OPTIMAL, Problem
 
     dev = torch.device("cuda:0")
-    lp = lpgen.config(WORKLOAD, seed=1)
-    tol = lpgen.tolerance(WORKLOAD)
+    if args.hbm_only:
+        print(json.dumps({"hbm_only": True, "hbm_bound": measure_hbm(dev)}), flush=True)
+        return
+    wl = args.kernels_workload if args.kernels_only else WORKLOAD
+    lp = lpgen.config(wl, seed=1)
+    tol = lpgen.tolerance(wl)
     m, n, nnz = lp.m, lp.n, lp.nnz
     pb, db = algorithmic_bytes(m, n, nnz)
-    log(f"# workload {WORKLOAD}: m={m} n={n} nnz={nnz} max_row={lp.meta['max_row']}")
+    log(f"# workload {wl}: m={m} n={n} nnz={nnz} max_row={lp.meta['max_row']}")
 
     t0 = time.perf_counter()
     prob = Problem(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, device=dev)
@@ -121,7 +166,7 @@ def main():
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"kernels_only": True, "primal_us": prof["primal_ms"] * 1e3,
+        print(json.dumps({"kernels_only": True, "workload": wl, "primal_us": prof["primal_ms"] * 1e3,
                           "dual_us": prof["dual_ms"] * 1e3, "iters": prof["iters"],
                           "primal_bytes": pb, "dual_bytes": db, "copy_bytes": 2 * a.numel() * 8,
                           "kernel_source_hash": kernel_source_hash()}), flush=True)
@@ -181,32 +226,7 @@ def main():
 
     hbm = None
     if not args.no_hbm:
-        lp3 = lpgen.config("c3b", seed=1)
-        m3, n3, nnz3 = lp3.m, lp3.n, lp3.nnz
-        log(f"# hbm-bound c3b: m={m3} n={n3} nnz={nnz3} max_row={lp3.meta['max_row']}")
-        t0 = time.perf_counter()
-        p3 = Problem(lp3.A, lp3.c, lp3.lc, lp3.uc, lp3.lv, lp3.uv, device=dev)
-        torch.cuda.synchronize()
-        s3 = time.perf_counter() - t0
-        del lp3
-        p3.solve(max_iter=64, tol=0.0, want_r=False)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        K3 = 640
-        p3.solve(max_iter=K3, tol=0.0, want_r=False)
-        torch.cuda.synchronize()
-        it_s = K3 / (time.perf_counter() - t0)
-        pr3 = p3.profile(iters=100)
-        pb3, db3 = algorithmic_bytes(m3, n3, nnz3)
-        hbm = {"workload": f"c3b: m={m3} n={n3} nnz={nnz3} Zipf(1.882) rows capped at 50,000, "
-                           f"values +-10^U[-3,3]", "setup_s": round(s3, 3), "iters_per_s": round(it_s, 1),
-               "primal_us": round(pr3["primal_ms"] * 1e3, 2), "dual_us": round(pr3["dual_ms"] * 1e3, 2),
-               "primal_gbs": round(pb3 / (pr3["primal_ms"] * 1e-3) / 1e9, 1),
-               "dual_gbs": round(db3 / (pr3["dual_ms"] * 1e-3) / 1e9, 1),
-               "iter_gbs": round((pb3 + db3) / (pr3["iter_ms"] * 1e-3) / 1e9, 1)}
-        hbm["iter_frac_of_peak"] = round(hbm["iter_gbs"] / HBM_PEAK_GBS, 4)
-        p3.close()
-        log(f"# hbm: {hbm}")
+        hbm = measure_hbm(dev)
 
     cpu = None
     if not args.no_cpu:
