@@ -100,6 +100,19 @@ typedef struct {
                               half-steps as non-temporal (streaming) data; 0: cached.
                               Automatic streams when both matrices exceed 128 MB.
                               Results are bitwise identical either way; -1 */
+  int32_t column_panels;   /* [setup] column panels for the dual half-step's A~ xbar:
+                              the nonzeros of long rows (more than panel_row_min) are
+                              also stored grouped by panels of consecutive columns,
+                              each panel reduced by blocks of one XCD so that its slice
+                              of xbar stays in that XCD's L2; the per-panel partial row
+                              sums are added in panel order.  -1: automatic (on when
+                              8n bytes exceed 8 MiB and long rows hold at least half of
+                              the nonzeros; then 8 ceil(n / 2^21) panels, so a panel's
+                              slice of xbar takes at most 2 MiB); 0: off;
+                              k > 0: 8 ceil(k / 8) panels, at most 1024.  Changes only the
+                              order in which the row sums are added; -1 */
+  int32_t panel_row_min;   /* [setup] rows with more nonzeros than this are "long"
+                              (>= 1); 16 */
 } hlp_params;
 
 /* Outcome of a solve.  Objectives and relative errors refer to the original
@@ -197,6 +210,11 @@ hlp_err hlp_lp_scaling(const hlp_lp* lp, double* d_r, double* d_c, double* eta, 
  * row_idx device int32[nnz], val device double[nnz] (the scaled values of the
  * transpose).  Any pointer may be NULL. */
 hlp_err hlp_lp_transpose(const hlp_lp* lp, int32_t* col_ptr, int32_t* row_idx, double* val);
+
+/* The column-panel layout chosen at setup (hlp_params::column_panels): the
+ * panel count (0: not used) and the number of long rows, through host
+ * pointers (either may be NULL).  Errors: HLP_EINVAL for a NULL handle. */
+hlp_err hlp_lp_panels(const hlp_lp* lp, int32_t* panels, int32_t* long_rows);
 
 /*
  * Unrolled iterations with a tape for the reverse mode (an extension: the

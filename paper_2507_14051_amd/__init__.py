@@ -14,7 +14,7 @@ import numpy as np
 
 from .hlp import (FP64, MIXED, HLP_OK, ITER_LIMIT, NUMERICAL, OPTIMAL, STATUS_NAMES, SYMBOLS, TIME_LIMIT,
                   HlpError, HlpInfo, HlpParams, hlp_last_error, hlp_lp_create, hlp_lp_destroy,
-                  hlp_lp_scaling, hlp_lp_transpose, hlp_lp_update_vectors, hlp_params_default,
+                  hlp_lp_panels, hlp_lp_scaling, hlp_lp_transpose, hlp_lp_update_vectors, hlp_params_default,
                   hlp_profile_iterations, hlp_solve, hlp_tape_bytes, hlp_unrolled_backward,
                   hlp_unrolled_forward, hlp_workspace_bytes, lib)
 
@@ -22,7 +22,7 @@ __all__ = ["Problem", "solve", "HlpError", "FP64", "MIXED", "OPTIMAL", "ITER_LIM
            "NUMERICAL", "STATUS_NAMES", "hlp_params_default"]
 
 SETUP_FIELDS = ("precision", "eta_override", "ruiz_iters", "pock_chambolle", "power_max_iter", "power_tol",
-                "stream_matrix")
+                "stream_matrix", "column_panels", "panel_row_min")
 
 
 def _dev_tensor(a, dtype, device):
@@ -124,6 +124,10 @@ class Problem:
         tv = torch.empty(self.nnz, dtype=torch.float64, device=self.device)
         hlp_lp_transpose(self.handle, cp, ri, tv)
         return cp, ri, tv
+
+    def panels(self):
+        """(panel count, long rows) of the column-panel layout; (0, 0) if unused."""
+        return hlp_lp_panels(self.handle)
 
     def profile(self, iters=200, **params):
         return hlp_profile_iterations(self.handle, self.params_for(**params), iters)

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "hlp_internal.h"
 
@@ -63,12 +64,31 @@ int lanes_for(double mean) {
   return L;
 }
 
-size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t precision) {
+int32_t panel_count(int32_t n, const hlp_params* p) {
+  int64_t P = 0;
+  if (p->column_panels > 0) P = 8 * (((int64_t)p->column_panels + 7) / 8);
+  else if (p->column_panels == -1 && n > (1 << 20)) P = 8 * (((int64_t)n + (1 << 21) - 1) >> 21);
+  return (int32_t)std::min<int64_t>(P, 1024);
+}
+
+size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t precision, int32_t panels,
+             int32_t panel_row_min) {
   Carver c{static_cast<char*>(base)};
   const bool mixed = precision == HLP_MIXED;
   const int64_t N = std::max<int64_t>(m, n);
   hlp_lp tmp;
   hlp_lp* L = lp ? lp : &tmp;
+  // panel layout capacity: at most nnz / (T + 1) rows are longer than T
+  int64_t nLmax = 0, R = 0;
+  if (panels > 0 && panel_row_min >= 1) {
+    nLmax = std::min<int64_t>(m, nnz / ((int64_t)panel_row_min + 1));
+    R = (int64_t)panels * nLmax;
+    if (R + 2 >= (int64_t(1) << 30)) nLmax = R = 0;  // int32 device indexing of the panel rows
+  }
+  if (nLmax == 0) panels = 0;
+  L->panels = panels;  // reserved count; hlp_lp_create may switch the layout off
+  L->nL_cap = (int32_t)nLmax;
+  const int64_t RB = std::max<int64_t>(N, R);
   L->rp = c.take<int32_t>((int64_t)m + 1);
   L->col = c.take<int32_t>(nnz);
   L->val0 = c.take<double>(nnz);
@@ -121,7 +141,8 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
   L->rbT = c.take<int32_t>((int64_t)n + 2);
   L->rbxA = c.take<int32_t>(4 * ((int64_t)m + 1));
   L->rbxT = c.take<int32_t>(4 * ((int64_t)n + 1));
-  L->rbtmp = c.take<int32_t>(2 * (N + 1));
+  L->rbtmp = c.take<int32_t>(2 * (RB + 1));
+  L->rbtmp_rows = RB;
   L->step = c.take<StepDev>(1);
   // reductions: 4 regions of partial_blocks x 8 doubles (at most one block per row)
   L->partial_blocks = N + 2;
@@ -138,8 +159,29 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
   const int64_t nbr = (nnz + 4095) / 4096;
   L->hist_len = 256 * std::max<int64_t>(nbr, 1);
   L->hist = c.take<int32_t>(L->hist_len);
-  L->scan_tmp_len = std::max<int64_t>(L->hist_len, N + 1) / 1024 + 2;
+  L->scan_tmp_len = std::max<int64_t>(L->hist_len, RB + 1) / 1024 + 2;
   L->scan_tmp = c.take<int32_t>(L->scan_tmp_len);
+  if (panels > 0) {
+    L->lrow = c.take<int32_t>(nLmax);
+    L->plid = c.take<int32_t>((int64_t)m + 1);
+    L->lbits = c.take<uint32_t>(((int64_t)m + 31) / 32);
+    L->sp = c.take<int32_t>((int64_t)m + 1);
+    L->scol = c.take<int32_t>(nnz);
+    L->sval = c.take<double>(nnz);
+    L->sval32 = mixed ? c.take<float>(nnz) : nullptr;
+    L->pp = c.take<int32_t>(R + 1);
+    L->pcol = c.take<int32_t>(nnz);
+    L->pval = c.take<double>(nnz);
+    L->pval32 = mixed ? c.take<float>(nnz) : nullptr;
+    L->ppart = c.take<double>(R);
+    L->rbS = c.take<int32_t>((int64_t)m + 2);
+    L->rbxS = c.take<int32_t>(4 * ((int64_t)m + 1));
+    L->rbP = c.take<int32_t>(R + 2);
+    L->rbxP = c.take<int32_t>(4 * (R + 1));
+    L->tabP = c.take<int32_t>(4 * (R + 1));
+    L->pscrA = c.take<int32_t>(std::max<int64_t>(m, R) + 1);
+    L->pscrB = c.take<int32_t>(std::max<int64_t>(m, R) + 1);
+  }
   // power iteration vectors alias iteration buffers (setup only)
   L->pv = L->rbuf;
   L->pw = L->atyc;
@@ -185,6 +227,8 @@ hlp_err hlp_params_default(hlp_params* p) {
   p->debug_poison_iter = 0;
   p->graphs = 1;
   p->stream_matrix = -1;
+  p->column_panels = -1;
+  p->panel_row_min = 16;
   return HLP_OK;
 }
 
@@ -209,12 +253,65 @@ hlp_err hlp_workspace_bytes(int32_t m, int32_t n, int64_t nnz, const hlp_params*
   hlp_params d;
   hlp_params_default(&d);
   if (!p) p = &d;
-  *bytes = carve(nullptr, nullptr, m, n, nnz, p->precision);
+  *bytes = carve(nullptr, nullptr, m, n, nnz, p->precision, panel_count(n, p), p->panel_row_min);
   return HLP_OK;
 }
 
 static hlp_err read_flags(hlp_lp* lp, int* out) {
   HLP_HIP(hipMemcpyAsync(out, lp->flags, sizeof(int), hipMemcpyDeviceToHost, lp->stream));
+  HLP_HIP(hipStreamSynchronize(lp->stream));
+  return HLP_OK;
+}
+
+// Column-panel layout of the long rows (see hlp_params::column_panels); P is
+// the reserved panel count.  Leaves lp->panels = 0 when the layout is not used.
+static hlp_err build_panels(hlp_lp* lp, int32_t P, int32_t T, bool automatic) {
+  lp->panels = 0;
+  if (P <= 0 || lp->m == 0 || lp->n == 0 || lp->nnz == 0) return HLP_OK;
+  HLP_HIP(launch_panel_split(lp, T, lp->flags));
+  int32_t cnt[4] = {0, 0, 0, 0};
+  HLP_HIP(hipMemcpyAsync(cnt, lp->flags, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, lp->stream));
+  HLP_HIP(hipStreamSynchronize(lp->stream));
+  const int32_t nL = cnt[0];
+  const int64_t nnz_long = lp->nnz - cnt[1];
+  if (nL < 1 || nL > lp->nL_cap) return HLP_OK;
+  if (automatic && 2 * nnz_long < lp->nnz) return HLP_OK;
+  lp->panels = P;
+  lp->nL = nL;
+  lp->panel_w = (int32_t)(((int64_t)lp->n + P - 1) / P);
+  HLP_HIP(launch_panel_layout(lp, lp->flags));
+  HLP_HIP(hipMemcpyAsync(cnt, lp->flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, lp->stream));
+  HLP_HIP(hipStreamSynchronize(lp->stream));
+  lp->nbS = cnt[2];
+  lp->nbP = cnt[3];
+  // blocks of panel p: [pstart[p], pstart[p+1]); dealt to XCD p mod 8 in panel order
+  std::vector<int32_t> pstart(P + 1);
+  HLP_HIP(launch_panel_starts(lp, lp->pscrA));
+  HLP_HIP(hipMemcpyAsync(pstart.data(), lp->pscrA, P * sizeof(int32_t), hipMemcpyDeviceToHost, lp->stream));
+  HLP_HIP(hipStreamSynchronize(lp->stream));
+  pstart[P] = lp->nbP;
+  int32_t off = 0, widest = 0;
+  for (int x = 0; x < 8; ++x) {
+    lp->poff[x] = off;
+    for (int q = x; q < P; q += 8) {
+      const int32_t len = pstart[q + 1] - pstart[q];
+      if (len < 1 || off + len > lp->nbP) {
+        set_error("column panels: inconsistent block table");
+        return HLP_EUNSUPPORTED;
+      }
+      HLP_HIP(hipMemcpyAsync(lp->tabP + 4 * (int64_t)off, lp->rbxP + 4 * (int64_t)pstart[q],
+                             16 * (size_t)len, hipMemcpyDeviceToDevice, lp->stream));
+      off += len;
+    }
+    widest = std::max(widest, off - lp->poff[x]);
+  }
+  lp->poff[8] = off;
+  if (off != lp->nbP) {
+    set_error("column panels: inconsistent block table");
+    return HLP_EUNSUPPORTED;
+  }
+  lp->nbPgrid = 8 * widest;
+  lp->nbC = (nL + 255) / 256;
   HLP_HIP(hipStreamSynchronize(lp->stream));
   return HLP_OK;
 }
@@ -272,7 +369,12 @@ hlp_err hlp_lp_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr,
     set_error("bad setup parameters (ruiz_iters >= 0, power_max_iter >= 1, power_tol >= 0, finite eta_override >= 0)");
     return HLP_EINVAL;
   }
-  size_t need = carve(nullptr, nullptr, m, n, nnz, p->precision);
+  if (p->column_panels < -1 || p->panel_row_min < 1) {
+    set_error("bad setup parameters (column_panels >= -1, panel_row_min >= 1)");
+    return HLP_EINVAL;
+  }
+  const int32_t P = panel_count(n, p);
+  size_t need = carve(nullptr, nullptr, m, n, nnz, p->precision, P, p->panel_row_min);
   if (workspace_bytes < need) {
     set_error("workspace too small: need " + std::to_string(need) + " bytes");
     return HLP_ENOMEM;
@@ -288,7 +390,7 @@ hlp_err hlp_lp_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr,
   lp->nnz = nnz;
   lp->stream = reinterpret_cast<hipStream_t>(hip_stream);
   lp->precision = p->precision;
-  carve(lp, workspace, m, n, nnz, p->precision);
+  carve(lp, workspace, m, n, nnz, p->precision, P, p->panel_row_min);
   auto fail = [&](hlp_err e) {
     delete lp;
     return e;
@@ -335,6 +437,7 @@ hlp_err hlp_lp_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr,
   // 3. rescaling of A, then the vectors
   if (hipError_t e = launch_rescale(lp, p->ruiz_iters, p->pock_chambolle); e != hipSuccess)
     return fail(hip_fail(e, "rescale"));
+  if (hlp_err e = build_panels(lp, P, p->panel_row_min, p->column_panels == -1); e != HLP_OK) return fail(e);
   if (hlp_err e = validate_and_scale_vectors(lp, c, lc, uc, lv, uv); e != HLP_OK) return fail(e);
   // 4. stepsize
   if (p->eta_override > 0.0) {
@@ -399,6 +502,16 @@ hlp_err hlp_lp_transpose(const hlp_lp* lp, int32_t* col_ptr, int32_t* row_idx, d
   if (val && lp->nnz)
     HLP_HIP(hipMemcpyAsync(val, lp->tval, sizeof(double) * lp->nnz, hipMemcpyDeviceToDevice, lp->stream));
   HLP_HIP(hipStreamSynchronize(lp->stream));
+  return HLP_OK;
+}
+
+hlp_err hlp_lp_panels(const hlp_lp* lp, int32_t* panels, int32_t* long_rows) {
+  if (!lp) {
+    set_error("NULL handle");
+    return HLP_EINVAL;
+  }
+  if (panels) *panels = lp->panels;
+  if (long_rows) *long_rows = lp->panels ? lp->nL : 0;
   return HLP_OK;
 }
 

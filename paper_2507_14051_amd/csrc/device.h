@@ -78,12 +78,14 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NQV], double* out
 // ---------------------------------------------------------------- row blocks
 // The hot SpMVs walk "row blocks" built at setup: each block covers at most
 // kRbRows consecutive rows whose nonzeros start in the same kRbCap-sized chunk
-// of the value array, and a row longer than kRbCap forms a block of its own.
-// So a block of short rows holds at most 2 kRbCap = kRbLds nonzeros, staged in
-// LDS; a long row is reduced by the whole block.
+// of the value array, and a row longer than kRbSerial forms a block of its own.
+// So a block of several rows holds at most kRbCap + kRbSerial = kRbLds
+// nonzeros, staged in LDS and summed per row by one thread (at most kRbSerial
+// terms); a single-row block is reduced by the whole block.
 constexpr int kRbRows = kBlock;
 constexpr int kRbCap = 2048;
-constexpr int kRbLds = 2 * kRbCap;
+constexpr int kRbSerial = 64;
+constexpr int kRbLds = kRbCap + kRbSerial;
 
 template <typename T>
 __device__ __forceinline__ T block_sum_to0(T v) {
@@ -98,10 +100,11 @@ __device__ __forceinline__ T block_sum_to0(T v) {
 }
 
 // Row sums of val .* vec[idx] over the calling block's rows [s, e) with
-// nonzeros [ps, pe).  In a block of short rows thread t returns the sum of
+// nonzeros [ps, pe).  In a block of several rows thread t returns the sum of
 // row s + t (products staged in LDS, then summed left to right); in a
-// single-row block every thread returns that row's sum (strided partials, a
-// fixed shuffle tree and the waves in order).  Deterministic either way.
+// single-row block (single = e - s == 1) every thread returns that row's sum
+// (strided partials, a fixed shuffle tree and the waves in order).
+// Deterministic either way.
 // Each thread handles the nonzeros ps + tid + k*kBlock in batches of kRbUnroll:
 // all index and value loads of a batch are issued, then all gathers, then the
 // products, so a thread has a whole batch of gathers in flight instead of one.
@@ -118,9 +121,9 @@ __device__ __forceinline__ T ld(const T* p) {
 template <typename ACC, bool NT = false, typename V, typename X>
 __device__ __forceinline__ ACC rb_dot(const int32_t* __restrict__ idx, const V* __restrict__ val,
                                       const X* __restrict__ vec, int ps, int pe, int a0, int a1,
-                                      bool own, ACC* lds) {
+                                      bool own, bool single, ACC* lds) {
   const int tid = threadIdx.x;
-  const bool staged = pe - ps <= kRbLds;
+  const bool staged = !single;  // block-uniform; several rows imply pe - ps <= kRbLds
   ACC part = 0;
   for (int base = ps + tid; base < pe; base += kBlock * kRbUnroll) {
     // Past the end, the clamped position repeats the last nonzero (a valid

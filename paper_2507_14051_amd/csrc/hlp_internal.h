@@ -81,6 +81,25 @@ struct hlp_lp {
   // matrices exceed half of the 256 MB Infinity Cache, so they do not evict
   // the gathered vectors)
   bool nt = false;
+  // Column panels of the long rows (dual half-step, see hlp_params::column_panels).
+  // AS: A~ without the long rows (they are empty rows there); AP: the nonzeros
+  // of the long rows grouped panel-major, AP row p*nL + l = the part of long
+  // row lrow[l] in panel p (columns [p*panel_w, (p+1)*panel_w)).
+  int32_t panels = 0, panel_w = 0, nL = 0, nL_cap = 0;
+  int32_t *lrow = nullptr, *plid = nullptr;
+  uint32_t* lbits = nullptr;          // bit i: row i is long
+  int32_t *sp = nullptr, *scol = nullptr;
+  double* sval = nullptr;
+  float* sval32 = nullptr;
+  int32_t *pp = nullptr, *pcol = nullptr;
+  double* pval = nullptr;
+  float* pval32 = nullptr;
+  double* ppart = nullptr;            // partial row sums, P*nL (float in the FP32 path)
+  int32_t *rbS = nullptr, *rbxS = nullptr, *rbP = nullptr, *rbxP = nullptr, *tabP = nullptr;
+  int32_t *pscrA = nullptr, *pscrB = nullptr;  // setup scratch
+  int32_t nbS = 0, nbP = 0, nbPgrid = 0, nbC = 0;
+  int32_t poff[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // blocks of XCD x: tabP[poff[x] .. poff[x+1])
+  int64_t rbtmp_rows = 0;             // capacity of the row-block scratch (rows)
   hlp::StepDev* step = nullptr;
   // captured runs of eval_freq iterations (see controller.cpp)
   void* graph_exec[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -135,7 +154,10 @@ hlp_err hip_fail(hipError_t e, const char* what);
 
 // ---------------------------------------------------------------- layout
 // Carve the workspace.  With lp->... == nullptr base, only computes the size.
-size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t precision);
+size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t precision, int32_t panels,
+             int32_t panel_row_min);
+// Panels reserved for these sizes and parameters (0: none).
+int32_t panel_count(int32_t n, const hlp_params* p);
 
 int lanes_for(double mean_row_len);
 
@@ -169,7 +191,12 @@ struct StepArgs {
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // if set: timestamps of the kernel itself
 };
 hipError_t launch_build_row_blocks(hlp_lp* lp, const int32_t* ptr, int32_t rows, int32_t* rb, int32_t* rbx,
-                                   int32_t* count);
+                                   int32_t* count, int32_t period = 0);
+// Column panels: long-row split (returns nL and the short-part nonzero count
+// through counts[0..1] on the device), then the panel layout and its blocks.
+hipError_t launch_panel_split(hlp_lp* lp, int32_t T, int32_t* counts);
+hipError_t launch_panel_layout(hlp_lp* lp, int32_t* counts);
+hipError_t launch_panel_starts(hlp_lp* lp, int32_t* pstart);
 hipError_t launch_set_step(hlp_lp* lp, double tau, double sigma, double gamma, int64_t k0, double P = 1.0,
                            double D = 1.0);
 hipError_t launch_primal(hlp_lp* lp, const StepArgs& s);

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kBlock) void k_primal(PrimalArgs p) {
     xj = p.x[j]; cj = p.ct[j]; lo = p.lv[j]; hi = p.uv[j]; xaj = p.xa[j];
     a0 = p.cp[j]; a1 = p.cp[j + 1];
   }
-  const double g = rb_dot<double, NT>(p.row, p.tval, p.y, ps, pe, a0, a1, own, lds);
+  const double g = rb_dot<double, NT>(p.row, p.tval, p.y, ps, pe, a0, a1, own, e - s == 1, lds);
   double q0 = 0.0, q1 = 0.0;
   if (own) {
     const double tau = p.step->tau, gam = p.step->gamma, a = halpern_a(p.step, p.j);
@@ -124,11 +124,11 @@ __global__ __launch_bounds__(kBlock) void k_dual(DualArgs p) {
     if (RES) dri = p.dr[i];
     a0 = p.rp[i]; a1 = p.rp[i + 1];
   }
-  const double h = rb_dot<double, NT>(p.col, p.val, p.xbar, ps, pe, a0, a1, own, lds);
+  const double h = rb_dot<double, NT>(p.col, p.val, p.xbar, ps, pe, a0, a1, own, e - s == 1, lds);
   double adx = 0.0, axh = 0.0;
   if (RES) {
-    adx = rb_dot<double>(p.col, p.val, p.dx, ps, pe, a0, a1, own, lds);
-    axh = rb_dot<double>(p.col, p.val, p.xh, ps, pe, a0, a1, own, lds);
+    adx = rb_dot<double>(p.col, p.val, p.dx, ps, pe, a0, a1, own, e - s == 1, lds);
+    axh = rb_dot<double>(p.col, p.val, p.xh, ps, pe, a0, a1, own, e - s == 1, lds);
   }
   double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (own) {
@@ -155,6 +155,133 @@ __global__ __launch_bounds__(kBlock) void k_dual(DualArgs p) {
   if (RES) block_reduce_store<5>(q, p.partials + (int64_t)blockIdx.x * kRegionStride);
 }
 
+// ---------------------------------------------------------------------------- column panels
+// Dual half-step with the long rows split into column panels (plain
+// iterations only).  k_panel_dot reduces each (panel, long row) segment; the
+// blocks of panel p run on XCD p mod 8 (workgroups are dealt to the XCDs in
+// turn), so an XCD gathers from one panel's slice of xbar at a time and the
+// slice stays in its L2.  k_dual_pn then does the short rows as k_dual does and,
+// in extra blocks, the long rows: h = sum of the panel partials in panel order.
+template <typename T>
+struct PanelDotArgs {
+  const int4* tab; const int32_t* pp; const int32_t* pcol; const T* pval; const T* vec; T* out;
+  int32_t off[9];
+};
+
+template <typename T, bool NT>
+__global__ __launch_bounds__(kBlock) void k_panel_dot(PanelDotArgs<T> p) {
+  __shared__ T lds[kRbLds];
+  const int x = blockIdx.x & 7;
+  const int k = p.off[x] + (int)(blockIdx.x >> 3);
+  if (k >= p.off[x + 1]) return;  // uniform over the block
+  const int4 blk = p.tab[k];
+  const int r = blk.x + threadIdx.x;
+  const bool own = r < blk.y;
+  int a0 = 0, a1 = 0;
+  if (own) { a0 = p.pp[r]; a1 = p.pp[r + 1]; }
+  const T acc = rb_dot<T, NT>(p.pcol, p.pval, p.vec, blk.z, blk.w, a0, a1, own, blk.y - blk.x == 1, lds);
+  if (own) p.out[r] = acc;
+}
+
+template <typename T>
+__device__ __forceinline__ T panel_sum(const T* __restrict__ part, int32_t P, int32_t nL, int l) {
+  T h = T(0);
+  for (int q = 0; q < P; q += 8) {  // P is a multiple of 8
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(q + u) * nL + l];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) h += v[u];
+  }
+  return h;
+}
+
+__device__ __forceinline__ bool is_long(const uint32_t* __restrict__ bits, int i) {
+  return (bits[i >> 5] >> (i & 31)) & 1u;
+}
+
+struct DualPanelArgs {
+  const int4* rb; const int32_t* sp; const int32_t* scol; const double* sval; const double* xbar;
+  double* y; const double* ya; const double* lc; const double* uc; const StepDev* step;
+  const uint32_t* lbits; const int32_t* lrow; const double* part;
+  int32_t P, nL, nbS, j;
+};
+
+template <bool NT>
+__global__ __launch_bounds__(kBlock) void k_dual_pn(DualPanelArgs p) {
+  __shared__ double lds[kRbLds];
+  int i = 0;
+  bool own = false;
+  double h = 0.0, yi = 0.0, lo = 0.0, hi = 0.0, yai = 0.0;
+  if ((int)blockIdx.x < p.nbS) {
+    const int4 blk = p.rb[blockIdx.x];
+    i = blk.x + threadIdx.x;
+    const bool in = i < blk.y;
+    int a0 = 0, a1 = 0;
+    if (in) {
+      a0 = p.sp[i]; a1 = p.sp[i + 1];
+      own = !is_long(p.lbits, i);
+      if (own) { yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i]; }
+    }
+    h = rb_dot<double, NT>(p.scol, p.sval, p.xbar, blk.z, blk.w, a0, a1, in, blk.y - blk.x == 1, lds);
+  } else {
+    const int l = ((int)blockIdx.x - p.nbS) * kBlock + threadIdx.x;
+    own = l < p.nL;
+    if (own) {
+      i = p.lrow[l];
+      yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i];
+      h = panel_sum(p.part, p.P, p.nL, l);
+    }
+  }
+  if (own) {
+    const double sigma = p.step->sigma, gam = p.step->gamma, a = halpern_a(p.step, p.j);
+    const double w = h - yi / sigma;
+    const double yh = sigma * (clampv(w, lo, hi) - w);
+    p.y[i] = a * ((1.0 + gam) * yh - gam * yi) + (1.0 - a) * yai;
+  }
+}
+
+struct Dual32PanelArgs {
+  const int4* rb; const int32_t* sp; const int32_t* scol; const float* sval; const float* xbar;
+  float* y; const float* ya; const float* lc; const float* uc; const float* b; const StepDev* step;
+  const uint32_t* lbits; const int32_t* lrow; const float* part;
+  int32_t P, nL, nbS, j;
+};
+
+template <bool NT>
+__global__ __launch_bounds__(kBlock) void k_dual32_pn(Dual32PanelArgs p) {
+  __shared__ float lds[kRbLds];
+  int i = 0;
+  bool own = false;
+  float h = 0.0f, yi = 0.0f, lo = 0.0f, hi = 0.0f, yai = 0.0f, bi = 0.0f;
+  if ((int)blockIdx.x < p.nbS) {
+    const int4 blk = p.rb[blockIdx.x];
+    i = blk.x + threadIdx.x;
+    const bool in = i < blk.y;
+    int a0 = 0, a1 = 0;
+    if (in) {
+      a0 = p.sp[i]; a1 = p.sp[i + 1];
+      own = !is_long(p.lbits, i);
+      if (own) { yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i]; bi = p.b[i]; }
+    }
+    h = rb_dot<float, NT>(p.scol, p.sval, p.xbar, blk.z, blk.w, a0, a1, in, blk.y - blk.x == 1, lds);
+  } else {
+    const int l = ((int)blockIdx.x - p.nbS) * kBlock + threadIdx.x;
+    own = l < p.nL;
+    if (own) {
+      i = p.lrow[l];
+      yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i]; bi = p.b[i];
+      h = panel_sum(p.part, p.P, p.nL, l);
+    }
+  }
+  if (own) {
+    const float sigma = (float)p.step->sigma, gam = (float)p.step->gamma, a = (float)halpern_a(p.step, p.j);
+    const float w = h - (bi + yi) / sigma;
+    const float yh = yi + sigma * (clampv(w, lo, hi) - h);
+    p.y[i] = a * ((1.0f + gam) * yh - gam * yi) + (1.0f - a) * yai;
+  }
+}
+
 // Column side of the KKT error at (xhat, yhat): g~ = c~ - A~^T yhat,
 // r~ = proj_R(g~), ||(g~ - r~)/d_c||^2, the column part of the dual objective,
 // c~^T xhat; in mixed mode also the max dual violation |g~ - r~| and the max
@@ -176,7 +303,7 @@ __global__ __launch_bounds__(kBlock) void k_kkt_cols(KktColArgs p) {
     a0 = p.cp[j];
     a1 = p.cp[j + 1];
   }
-  const double acc = rb_dot<double>(p.row, p.tval, p.yh, p.cp[s], p.cp[e], a0, a1, own, lds);
+  const double acc = rb_dot<double>(p.row, p.tval, p.yh, p.cp[s], p.cp[e], a0, a1, own, e - s == 1, lds);
   double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (own) {
     const double g = p.ct[j] - acc;
@@ -223,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_kkt_rows(KktRowArgs p) {
     a0 = p.rp[i];
     a1 = p.rp[i + 1];
   }
-  const double acc = rb_dot<double>(p.col, p.val, p.xh, p.rp[s], p.rp[e], a0, a1, own, lds);
+  const double acc = rb_dot<double>(p.col, p.val, p.xh, p.rp[s], p.rp[e], a0, a1, own, e - s == 1, lds);
   double q[3] = {0.0, 0.0, 0.0};
   if (own) {
     const double lo = p.lc[i], hi = p.uc[i];
@@ -263,7 +390,7 @@ __global__ __launch_bounds__(kBlock) void k_primal32(Primal32Args p) {
     xj = p.x[j]; cj = p.c[j]; lo = p.lv[j]; hi = p.uv[j]; xaj = p.xa[j];
     a0 = p.cp[j]; a1 = p.cp[j + 1];
   }
-  const float g = rb_dot<float, NT>(p.row, p.tval, p.y, ps, pe, a0, a1, own, lds);
+  const float g = rb_dot<float, NT>(p.row, p.tval, p.y, ps, pe, a0, a1, own, e - s == 1, lds);
   double q0 = 0.0, q1 = 0.0;
   if (own) {
     const float tau = (float)p.step->tau, gam = (float)p.step->gamma, a = (float)halpern_a(p.step, p.j);
@@ -307,9 +434,9 @@ __global__ __launch_bounds__(kBlock) void k_dual32(Dual32Args p) {
     yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i]; bi = p.b[i];
     a0 = p.rp[i]; a1 = p.rp[i + 1];
   }
-  const float h = rb_dot<float, NT>(p.col, p.val, p.xbar, ps, pe, a0, a1, own, reinterpret_cast<float*>(lds));
+  const float h = rb_dot<float, NT>(p.col, p.val, p.xbar, ps, pe, a0, a1, own, e - s == 1, reinterpret_cast<float*>(lds));
   double adx = 0.0;
-  if (RES) adx = rb_dot<double>(p.col, p.val, p.dx, ps, pe, a0, a1, own, lds);
+  if (RES) adx = rb_dot<double>(p.col, p.val, p.dx, ps, pe, a0, a1, own, e - s == 1, lds);
   double q[3] = {0.0, 0.0, 0.0};
   if (own) {
     const float sigma = (float)p.step->sigma, gam = (float)p.step->gamma, a = (float)halpern_a(p.step, p.j);
@@ -481,11 +608,27 @@ Region make_region(const double* p, int64_t nb, std::initializer_list<int> qs, u
 // end timestamps (for the per-kernel timing of hlp_profile_iterations).
 template <typename K, typename A>
 hipError_t launch_step_kernel(K kernel, int32_t nblk, const StepArgs& s, hipStream_t st, const A& a) {
-  if (s.ev_start)
+  if (s.ev_start || s.ev_stop)
     hipExtLaunchKernelGGL(kernel, dim3(nblk), dim3(kBlock), 0, st, s.ev_start, s.ev_stop, 0, a);
   else
     hipLaunchKernelGGL(kernel, dim3(nblk), dim3(kBlock), 0, st, a);
   return hipGetLastError();
+}
+
+// The two launches of a panel half-step; with events, the start event takes
+// the first kernel's start and the stop event the second kernel's end.
+template <typename T, typename KD, typename AD>
+hipError_t launch_panel_pair(hlp_lp* lp, const T* pval, const T* vec, KD kdual, const AD& ad, const StepArgs& s) {
+  PanelDotArgs<T> pa{reinterpret_cast<const int4*>(lp->tabP), lp->pp, lp->pcol, pval, vec,
+                     reinterpret_cast<T*>(lp->ppart), {}};
+  for (int k = 0; k < 9; ++k) pa.off[k] = lp->poff[k];
+  StepArgs s1 = s, s2 = s;
+  s1.ev_stop = nullptr;
+  s2.ev_start = nullptr;
+  hipError_t e = lp->nt ? launch_step_kernel(k_panel_dot<T, true>, lp->nbPgrid, s1, lp->stream, pa)
+                        : launch_step_kernel(k_panel_dot<T, false>, lp->nbPgrid, s1, lp->stream, pa);
+  if (e != hipSuccess) return e;
+  return launch_step_kernel(kdual, lp->nbS + lp->nbC, s2, lp->stream, ad);
 }
 
 }  // namespace
@@ -512,6 +655,12 @@ hipError_t launch_dual(hlp_lp* lp, const StepArgs& s) {
              lp->dr, lp->yh, region(lp, R_DUAL), s.mask_y, lp->step, s.j};
   if (s.mask_y) return launch_step_kernel(k_dual<2, false>, lp->nbA, s, lp->stream, a);
   if (s.residual) return launch_step_kernel(k_dual<1, false>, lp->nbA, s, lp->stream, a);
+  if (lp->panels) {
+    DualPanelArgs d{reinterpret_cast<const int4*>(lp->rbxS), lp->sp, lp->scol, lp->sval, lp->xbar, lp->y, lp->ya,
+                    lp->lct, lp->uct, lp->step, lp->lbits, lp->lrow, lp->ppart, lp->panels, lp->nL, lp->nbS, s.j};
+    return lp->nt ? launch_panel_pair<double>(lp, lp->pval, lp->xbar, k_dual_pn<true>, d, s)
+                  : launch_panel_pair<double>(lp, lp->pval, lp->xbar, k_dual_pn<false>, d, s);
+  }
   if (lp->nt) return launch_step_kernel(k_dual<0, true>, lp->nbA, s, lp->stream, a);
   return launch_step_kernel(k_dual<0, false>, lp->nbA, s, lp->stream, a);
 }
@@ -617,6 +766,14 @@ hipError_t launch_dual32(hlp_lp* lp, const StepArgs& s) {
   Dual32Args a{reinterpret_cast<const int4*>(lp->rbxA), lp->rp, lp->col, lp->val32, lp->xbar32, lp->dx32, lp->y32, lp->ya32, lp->lc32, lp->uc32,
                lp->b32, lp->yh32, region(lp, R_DUAL), lp->step, s.j};
   if (s.residual) return launch_step_kernel(k_dual32<true, false>, lp->nbA, s, lp->stream, a);
+  if (lp->panels) {
+    const float* part = reinterpret_cast<const float*>(lp->ppart);
+    Dual32PanelArgs d{reinterpret_cast<const int4*>(lp->rbxS), lp->sp, lp->scol, lp->sval32, lp->xbar32, lp->y32,
+                      lp->ya32, lp->lc32, lp->uc32, lp->b32, lp->step, lp->lbits, lp->lrow, part, lp->panels, lp->nL,
+                      lp->nbS, s.j};
+    return lp->nt ? launch_panel_pair<float>(lp, lp->pval32, lp->xbar32, k_dual32_pn<true>, d, s)
+                  : launch_panel_pair<float>(lp, lp->pval32, lp->xbar32, k_dual32_pn<false>, d, s);
+  }
   if (lp->nt) return launch_step_kernel(k_dual32<false, true>, lp->nbA, s, lp->stream, a);
   return launch_step_kernel(k_dual32<false, false>, lp->nbA, s, lp->stream, a);
 }

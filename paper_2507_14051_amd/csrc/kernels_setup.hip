@@ -258,14 +258,17 @@ __global__ void k_gather_transpose(const int32_t* __restrict__ perm, const int32
 // ----------------------------------------------------------------- row blocks
 // Row r starts a block if r is a multiple of kRbRows, if its nonzeros start in
 // another kRbCap-sized chunk than those of row r-1, or if row r or row r-1 is
-// longer than kRbCap (long rows stand alone).
-__global__ void k_rb_flags(const int32_t* __restrict__ ptr, int32_t rows, int32_t* __restrict__ flags) {
+// longer than kRbSerial (such rows stand alone); with period > 0 also every
+// period-th row (the first row of each column panel).
+__global__ void k_rb_flags(const int32_t* __restrict__ ptr, int32_t rows, int32_t period,
+                           int32_t* __restrict__ flags) {
   int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (r >= rows) return;
   int f = 1;
   if (r > 0) {
     const int p0 = ptr[r - 1], p1 = ptr[r], p2 = ptr[r + 1];
-    f = (r % kRbRows == 0) || (p1 / kRbCap != p0 / kRbCap) || (p1 - p0 > kRbCap) || (p2 - p1 > kRbCap);
+    f = (r % kRbRows == 0) || (p1 / kRbCap != p0 / kRbCap) || (p1 - p0 > kRbSerial) ||
+        (p2 - p1 > kRbSerial) || (period > 0 && r % period == 0);
   }
   flags[r] = f;
 }
@@ -292,6 +295,119 @@ __global__ void k_rb_expand(const int32_t* __restrict__ rb, const int32_t* __res
   rbx[4 * b + 1] = e;
   rbx[4 * b + 2] = ptr[s];
   rbx[4 * b + 3] = ptr[e];
+}
+
+// ----------------------------------------------------------------- column panels
+// Long rows (more than T nonzeros): fl[i] = 1; the short part keeps the other
+// rows' lengths.  Both arrays get a terminal 0 so their exclusive scans end
+// with the totals.
+__global__ void k_pn_flags(const int32_t* __restrict__ rp, int32_t m, int32_t T, int32_t* __restrict__ fl,
+                           int32_t* __restrict__ slen) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i > m) return;
+  if (i == m) {
+    fl[m] = 0;
+    slen[m] = 0;
+    return;
+  }
+  const int len = rp[i + 1] - rp[i];
+  const int lg = len > T;
+  fl[i] = lg;
+  slen[i] = lg ? 0 : len;
+}
+
+__global__ void k_pn_counts(const int32_t* __restrict__ plid, const int32_t* __restrict__ sp, int32_t m,
+                            int32_t* __restrict__ counts) {
+  counts[0] = plid[m];
+  counts[1] = sp[m];
+}
+
+// Short rows copied into AS (in order); long rows listed in lrow.
+__global__ void k_pn_short(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                           const double* __restrict__ val, const float* __restrict__ val32,
+                           const int32_t* __restrict__ plid, const int32_t* __restrict__ sp, int32_t m,
+                           int32_t* __restrict__ scol, double* __restrict__ sval, float* __restrict__ sval32,
+                           int32_t* __restrict__ lrow) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= m) return;
+  if (plid[i + 1] != plid[i]) {
+    lrow[plid[i]] = (int32_t)i;
+    return;
+  }
+  const int b = rp[i], d = sp[i] - b;
+  for (int q = b; q < rp[i + 1]; ++q) {
+    scol[q + d] = col[q];
+    sval[q + d] = val[q];
+    if (val32) sval32[q + d] = val32[q];
+  }
+}
+
+__global__ void k_pn_bits(const int32_t* __restrict__ plid, int32_t m, uint32_t* __restrict__ bits) {
+  int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (w >= ((int64_t)m + 31) / 32) return;
+  uint32_t b = 0;
+  for (int k = 0; k < 32; ++k) {
+    const int64_t i = w * 32 + k;
+    if (i < m && plid[i + 1] != plid[i]) b |= 1u << k;
+  }
+  bits[w] = b;
+}
+
+// first position q in [lo, hi) with col[q] >= c (columns increase within a row)
+__device__ int lower_col(const int32_t* __restrict__ col, int lo, int hi, int64_t c) {
+  while (lo < hi) {
+    const int mid = lo + (hi - lo) / 2;
+    if (col[mid] < c) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Segment t = p*nL + l: the nonzeros of long row lrow[l] with columns in
+// panel p; its length (terminal 0 at t = P*nL) and its first position in A~.
+__global__ void k_pn_seg(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                         const int32_t* __restrict__ lrow, int32_t nL, int32_t P, int32_t W,
+                         int32_t* __restrict__ seglen, int32_t* __restrict__ seg0) {
+  int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t R = (int64_t)P * nL;
+  if (t > R) return;
+  if (t == R) {
+    seglen[R] = 0;
+    return;
+  }
+  const int p = (int)(t / nL), l = (int)(t % nL);
+  const int i = lrow[l];
+  const int a = rp[i], b = rp[i + 1];
+  const int lo = lower_col(col, a, b, (int64_t)p * W);
+  const int hi = lower_col(col, lo, b, (int64_t)(p + 1) * W);
+  seglen[t] = hi - lo;
+  seg0[t] = lo;
+}
+
+// One block per long row: each nonzero to its panel's segment, order kept.
+__global__ void k_pn_long(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                          const double* __restrict__ val, const float* __restrict__ val32,
+                          const int32_t* __restrict__ lrow, int32_t nL, int32_t W, const int32_t* __restrict__ pp,
+                          const int32_t* __restrict__ seg0, int32_t* __restrict__ pcol, double* __restrict__ pval,
+                          float* __restrict__ pval32) {
+  const int l = blockIdx.x;
+  const int i = lrow[l];
+  for (int q = rp[i] + threadIdx.x; q < rp[i + 1]; q += kBlock) {
+    const int j = col[q];
+    const int64_t t = (int64_t)(j / W) * nL + l;
+    const int dst = pp[t] + (q - seg0[t]);
+    pcol[dst] = j;
+    pval[dst] = val[q];
+    if (val32) pval32[dst] = val32[q];
+  }
+}
+
+// First block of each panel (panels start blocks: see k_rb_flags).
+__global__ void k_pn_starts(const int32_t* __restrict__ rbx, int32_t nb, int32_t nL, int32_t* __restrict__ pstart) {
+  int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (b >= nb) return;
+  const int s = rbx[4 * b];
+  if (s % nL == 0) pstart[s / nL] = (int32_t)b;
 }
 
 // ----------------------------------------------------------------- rescaling
@@ -399,7 +515,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_plain(const int32_t* __restrict
     a0 = ptr[i];
     a1 = ptr[i + 1];
   }
-  const double v = rb_dot<double>(idx, val, x, ptr[s], ptr[e], a0, a1, own, lds);
+  const double v = rb_dot<double>(idx, val, x, ptr[s], ptr[e], a0, a1, own, e - s == 1, lds);
   double q[1] = {0.0};
   if (own) {
     out[i] = v;
@@ -604,18 +720,63 @@ hipError_t launch_transpose(hlp_lp* lp) {
 }
 
 hipError_t launch_build_row_blocks(hlp_lp* lp, const int32_t* ptr, int32_t rows, int32_t* rb, int32_t* rbx,
-                                   int32_t* count) {
+                                   int32_t* count, int32_t period) {
   if (rows == 0) return hipSuccess;
+  if (rows > lp->rbtmp_rows) return hipErrorInvalidValue;
   hipStream_t s = lp->stream;
   int32_t* flags = lp->rbtmp;
-  int32_t* pos = lp->rbtmp + ((int64_t)(lp->m > lp->n ? lp->m : lp->n) + 1);
-  hipLaunchKernelGGL(k_rb_flags, dim3(nblocks(rows)), dim3(kBlock), 0, s, ptr, rows, flags);
+  int32_t* pos = lp->rbtmp + (lp->rbtmp_rows + 1);
+  hipLaunchKernelGGL(k_rb_flags, dim3(nblocks(rows)), dim3(kBlock), 0, s, ptr, rows, period, flags);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if ((e = scan_exclusive(flags, pos, rows, lp->scan_tmp, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_rb_scatter, dim3(nblocks(rows)), dim3(kBlock), 0, s, flags, pos, rows, rb, count);
   hipLaunchKernelGGL(k_rb_expand, dim3(nblocks(rows)), dim3(kBlock), 0, s, rb, ptr, rows, (const int32_t*)count,
                      rbx);
+  return hipGetLastError();
+}
+
+hipError_t launch_panel_split(hlp_lp* lp, int32_t T, int32_t* counts) {
+  hipStream_t s = lp->stream;
+  const int32_t m = lp->m;
+  hipLaunchKernelGGL(k_pn_flags, dim3(nblocks((int64_t)m + 1)), dim3(kBlock), 0, s, lp->rp, m, T, lp->pscrA,
+                     lp->pscrB);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = scan_exclusive(lp->pscrA, lp->plid, (int64_t)m + 1, lp->scan_tmp, s)) != hipSuccess) return e;
+  if ((e = scan_exclusive(lp->pscrB, lp->sp, (int64_t)m + 1, lp->scan_tmp, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pn_counts, dim3(1), dim3(1), 0, s, lp->plid, lp->sp, m, counts);
+  return hipGetLastError();
+}
+
+// Needs lp->panels, panel_w and nL set (nL <= nL_cap); block counts of AS and
+// AP go to counts[2] and counts[3].
+hipError_t launch_panel_layout(hlp_lp* lp, int32_t* counts) {
+  hipStream_t s = lp->stream;
+  const int32_t m = lp->m, nL = lp->nL, P = lp->panels, W = lp->panel_w;
+  const int64_t R = (int64_t)P * nL;
+  if (nL < 1 || nL > lp->nL_cap || R + 1 > lp->rbtmp_rows + 1) return hipErrorInvalidValue;
+  const float* v32 = lp->precision == HLP_MIXED ? lp->val32 : nullptr;
+  hipLaunchKernelGGL(k_pn_short, dim3(nblocks(m)), dim3(kBlock), 0, s, lp->rp, lp->col, lp->val, v32, lp->plid,
+                     lp->sp, m, lp->scol, lp->sval, lp->sval32, lp->lrow);
+  hipLaunchKernelGGL(k_pn_bits, dim3(nblocks(((int64_t)m + 31) / 32)), dim3(kBlock), 0, s, lp->plid, m,
+                     lp->lbits);
+  hipLaunchKernelGGL(k_pn_seg, dim3(nblocks(R + 1)), dim3(kBlock), 0, s, lp->rp, lp->col, lp->lrow, nL, P, W,
+                     lp->pscrA, lp->pscrB);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = scan_exclusive(lp->pscrA, lp->pp, R + 1, lp->scan_tmp, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pn_long, dim3(nL), dim3(kBlock), 0, s, lp->rp, lp->col, lp->val, v32, lp->lrow, nL, W,
+                     lp->pp, lp->pscrB, lp->pcol, lp->pval, lp->pval32);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_build_row_blocks(lp, lp->sp, m, lp->rbS, lp->rbxS, counts + 2)) != hipSuccess) return e;
+  return launch_build_row_blocks(lp, lp->pp, (int32_t)R, lp->rbP, lp->rbxP, counts + 3, nL);
+}
+
+hipError_t launch_panel_starts(hlp_lp* lp, int32_t* pstart) {
+  if (lp->nbP < 1 || lp->nL < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pn_starts, dim3(nblocks(lp->nbP)), dim3(kBlock), 0, lp->stream, lp->rbxP, lp->nbP, lp->nL,
+                     pstart);
   return hipGetLastError();
 }
 

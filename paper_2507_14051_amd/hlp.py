@@ -19,7 +19,7 @@ STATUS_NAMES = {OPTIMAL: "OPTIMAL", ITER_LIMIT: "ITER_LIMIT", TIME_LIMIT: "TIME_
 
 # The exported symbols, in the order of include/hlp.h.
 SYMBOLS = ("hlp_params_default", "hlp_workspace_bytes", "hlp_lp_create", "hlp_lp_update_vectors",
-           "hlp_solve", "hlp_lp_scaling", "hlp_lp_transpose", "hlp_tape_bytes", "hlp_unrolled_forward",
+           "hlp_solve", "hlp_lp_scaling", "hlp_lp_transpose", "hlp_lp_panels", "hlp_tape_bytes", "hlp_unrolled_forward",
            "hlp_unrolled_backward", "hlp_profile_iterations", "hlp_lp_destroy", "hlp_last_error")
 
 
@@ -33,7 +33,7 @@ class HlpParams(C.Structure):
         ("ruiz_iters", C.c_int32), ("pock_chambolle", C.c_int32), ("power_max_iter", C.c_int32),
         ("restart_to_current", C.c_int32), ("power_tol", C.c_double), ("pid_min_norm", C.c_double),
         ("trace_iters", C.c_int32), ("debug_poison_iter", C.c_int32), ("graphs", C.c_int32),
-        ("stream_matrix", C.c_int32),
+        ("stream_matrix", C.c_int32), ("column_panels", C.c_int32), ("panel_row_min", C.c_int32),
     ]
 
 
@@ -74,6 +74,7 @@ def lib():
         L.hlp_solve.argtypes = [P, C.POINTER(HlpParams), P, P, P, P, P, C.POINTER(HlpInfo), P]
         L.hlp_lp_scaling.argtypes = [P, P, P, C.POINTER(C.c_double), C.POINTER(I32)]
         L.hlp_lp_transpose.argtypes = [P, P, P, P]
+        L.hlp_lp_panels.argtypes = [P, C.POINTER(I32), C.POINTER(I32)]
         L.hlp_tape_bytes.argtypes = [P, I32, I32, C.POINTER(SZ)]
         L.hlp_unrolled_forward.argtypes = [P, C.POINTER(HlpParams), I32, I32, I32, P, P, P, P, P, SZ]
         L.hlp_unrolled_backward.argtypes = [P, P, SZ] + [P] * 7
@@ -149,6 +150,12 @@ def hlp_lp_scaling(lp, d_r=None, d_c=None):
     it = C.c_int32(0)
     _check(lib().hlp_lp_scaling(lp, _ptr(d_r), _ptr(d_c), C.byref(eta), C.byref(it)))
     return eta.value, it.value
+
+
+def hlp_lp_panels(lp):
+    P, nl = C.c_int32(0), C.c_int32(0)
+    _check(lib().hlp_lp_panels(lp, C.byref(P), C.byref(nl)))
+    return P.value, nl.value
 
 
 def hlp_lp_transpose(lp, col_ptr=None, row_idx=None, val=None):

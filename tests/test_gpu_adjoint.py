@@ -58,8 +58,8 @@ def test_gradients_match_oracle(seed):
 
 
 def test_gradients_long_rows_match_oracle():
-    """Rows longer than the LDS stage take the block-wide reduction path in the
-    reverse kernels too."""
+    """Rows longer than 64 nonzeros (some beyond the LDS stage) take the
+    block-wide reduction path in the reverse kernels too."""
     lp = lpgen.gen(1500, 12000, zipf_alpha=1.3, cap=6000, eq_frac=0.3, free_frac=0.2, values="normal", seed=9)
     assert (np.diff(lp.A.indptr) > 4096).sum() > 10
     K, ckpt = 120, 25

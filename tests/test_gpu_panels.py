@@ -1,0 +1,182 @@
+"""GPU parity of the column-panel dual half-step (long rows split by column
+panels, partial row sums added in panel order) against the FP64 oracle and
+against the unsplit GPU path.
+
+The panel kernels run in the plain iterations of a run; the first and last
+iteration of each run of eval_freq iterations (and traced ones) take the
+check kernels.  So the end point after K iterations is compared, for K inside
+one run (63: 61 panel iterations) and across several runs and restarts.  Bars:
+1e-10 relative to the oracle (only the summation order differs), 1e-12 to the
+unsplit GPU path, bitwise repeatable, graphs bitwise equal to direct launches.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import lpgen
+import oracle
+from oracle.pdhg import Params
+from tests._gpu import announce, np_out, problem, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _lp_from_matrix(A, seed, eq_frac=0.3):
+    """Bounds and costs around a given matrix, as in the generator's recipe."""
+    rng = np.random.default_rng(seed)
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    m, n = A.shape
+    xhat = rng.random(n)
+    b = A @ xhat
+    neq = int(eq_frac * m)
+    lc = b.copy()
+    uc = b.copy()
+    lc[neq:] = b[neq:] - rng.random(m - neq)
+    uc[neq:] = np.inf
+    return lpgen.LP(A=A, c=rng.standard_normal(n), lc=lc, uc=uc, lv=np.zeros(n), uv=np.ones(n), xhat=xhat)
+
+
+def _random_rows(rng, m, n, lengths):
+    rows, cols = [], []
+    for i, L in enumerate(lengths):
+        L = int(min(L, n))
+        if L == 0:
+            continue
+        cols.append(rng.choice(n, size=L, replace=False))
+        rows.append(np.full(L, i))
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    return sp.csr_matrix((rng.standard_normal(r.size), (r, c)), shape=(m, n))
+
+
+def _end_point_case(lp, K, panels, row_min, precision_mixed=False):
+    prob = problem(lp, column_panels=panels, panel_row_min=row_min)
+    P, nl = prob.panels()
+    lens = np.diff(lp.A.indptr)
+    assert P == 8 * ((panels + 7) // 8) and nl == int((lens > row_min).sum()) > 0
+    _, _, eta, _ = prob.scaling()
+    out = np_out(prob.solve(tol=0.0, max_iter=K))
+    prob.close()
+    plain = problem(lp, column_panels=0)
+    assert plain.panels() == (0, 0)
+    ref_gpu = np_out(plain.solve(tol=0.0, max_iter=K))
+    plain.close()
+    ref = oracle.solve(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, Params(tol=0.0, max_iter=K, eta_override=eta))
+    ex, ey = rel(out["x"], ref.x), rel(out["y"], ref.y)
+    gx, gy = rel(out["x"], ref_gpu["x"]), rel(out["y"], ref_gpu["y"])
+    print(f"K={K} P={P} long rows={nl}: vs oracle {ex:.1e} {ey:.1e}; vs unsplit {gx:.1e} {gy:.1e}")
+    assert ex <= TOL and ey <= TOL
+    assert gx <= 1e-12 and gy <= 1e-12
+    assert out["info"]["restarts"] == ref.restarts
+    assert out["info"]["omega"] == pytest.approx(ref.omega, rel=1e-9)
+    return out, ref
+
+
+@pytest.mark.parametrize("K", [63, 200])
+def test_panels_skewed_rows_match_oracle(K):
+    """Zipf rows up to 9,000 nonzeros: segments longer than the LDS stage take
+    the block-wide reduction, short segments share blocks."""
+    lp = lpgen.gen(3000, 20000, zipf_alpha=1.3, cap=9000, eq_frac=0.3, free_frac=0.2, values="normal", seed=7)
+    announce(f"panels skewed K={K} nnz={lp.nnz}")
+    _end_point_case(lp, K, panels=16, row_min=8)
+
+
+def test_panels_all_rows_long():
+    """panel_row_min below every row length: the short part is empty."""
+    lp = lpgen.config("c1", seed=2)
+    announce("panels all rows long (c1)")
+    _end_point_case(lp, 200, panels=8, row_min=2)
+
+
+def test_panels_single_long_row_and_empty_rows():
+    rng = np.random.default_rng(11)
+    m, n = 700, 6000
+    lens = rng.integers(0, 6, size=m)
+    lens[::37] = 0
+    lens[5] = 5000                      # the one long row; its segments exceed the LDS stage
+    lp = _lp_from_matrix(_random_rows(rng, m, n, lens), seed=11)
+    announce(f"panels single long row nnz={lp.nnz}")
+    _end_point_case(lp, 63, panels=8, row_min=16)
+
+
+def test_panels_more_panels_than_columns():
+    """n = 10 < 16 panels: panels of width 1, six of them empty."""
+    rng = np.random.default_rng(5)
+    m, n = 60, 10
+    lens = rng.integers(1, 11, size=m)
+    lp = _lp_from_matrix(_random_rows(rng, m, n, lens), seed=5)
+    announce("panels P > n")
+    _end_point_case(lp, 200, panels=16, row_min=4)
+
+
+def test_panels_fp64_solve_to_tolerance_and_repeatable():
+    lp = lpgen.config("c1", seed=3)
+    announce("panels c1 solve 1e-8")
+    prob = problem(lp, column_panels=8, panel_row_min=3)
+    assert prob.panels()[0] == 8
+    _, _, eta, _ = prob.scaling()
+    a = np_out(prob.solve(tol=1e-8))
+    b = np_out(prob.solve(tol=1e-8))
+    c = np_out(prob.solve(tol=1e-8, graphs=0))
+    prob.close()
+    for k in ("x", "y"):
+        assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k])
+    ref = oracle.solve(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, Params(tol=1e-8, eta_override=eta))
+    assert a["info"]["status"] == oracle.pdhg.OPTIMAL == ref.status
+    assert a["info"]["iters"] == ref.iters and a["info"]["restarts"] == ref.restarts
+    k = oracle.kkt(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, a["x"], a["y"])
+    assert k["rel_kkt"] <= 1e-8 * (1 + 1e-6)
+    assert rel(a["x"], ref.x) <= 1e-8 and rel(a["y"], ref.y) <= 1e-8
+
+
+def test_panels_mixed_precision():
+    """FP32 panel path: same tolerance by the oracle's KKT; graphs bitwise equal
+    to direct launches; close to the unsplit FP32 path."""
+    from paper_2507_14051_amd import MIXED
+    lp = lpgen.gen(3000, 20000, zipf_alpha=1.3, cap=9000, eq_frac=0.3, free_frac=0.2, values="normal", seed=7)
+    announce("panels mixed")
+    prob = problem(lp, precision=MIXED, column_panels=16, panel_row_min=8)
+    assert prob.panels()[0] == 16
+    a = np_out(prob.solve(tol=0.0, max_iter=300))
+    b = np_out(prob.solve(tol=0.0, max_iter=300, graphs=0))
+    prob.close()
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["y"], b["y"])
+    plain = problem(lp, precision=MIXED, column_panels=0)
+    c = np_out(plain.solve(tol=0.0, max_iter=300))
+    plain.close()
+    print(f"mixed panels vs unsplit after 300: x {rel(a['x'], c['x']):.1e} y {rel(a['y'], c['y']):.1e}")
+    assert rel(a["x"], c["x"]) <= 1e-4 and rel(a["y"], c["y"]) <= 1e-4
+    lp1 = lpgen.config("c1", seed=1)
+    p1 = problem(lp1, precision=MIXED, column_panels=8, panel_row_min=3)
+    o = np_out(p1.solve(tol=1e-8))
+    p1.close()
+    k = oracle.kkt(lp1.A, lp1.c, lp1.lc, lp1.uc, lp1.lv, lp1.uv, o["x"], o["y"])
+    assert o["info"]["status"] == oracle.pdhg.OPTIMAL and k["rel_kkt"] <= 1e-8 * (1 + 1e-6)
+
+
+def test_panels_automatic_on_large_skewed_lp():
+    """The large skewed LP (m=2e6, n=5e6, ~30M nonzeros): the automatic rule
+    takes 24 panels; 200 iterations agree with the unsplit path."""
+    lp = lpgen.config("c3b", seed=1)
+    announce(f"panels c3b nnz={lp.nnz}")
+    a = problem(lp)
+    P, nl = a.panels()
+    assert P == 24 and nl == int((np.diff(lp.A.indptr) > 16).sum())
+    oa = np_out(a.solve(tol=0.0, max_iter=200))
+    a.close()
+    b = problem(lp, column_panels=0)
+    ob = np_out(b.solve(tol=0.0, max_iter=200))
+    b.close()
+    print(f"c3b panels vs unsplit: x {rel(oa['x'], ob['x']):.1e} y {rel(oa['y'], ob['y']):.1e}")
+    assert rel(oa["x"], ob["x"]) <= 1e-10 and rel(oa["y"], ob["y"]) <= 1e-10
+    assert oa["info"]["restarts"] == ob["info"]["restarts"]
+
+
+def test_panels_off_by_default_on_small_lp():
+    lp = lpgen.config("c1", seed=1)
+    prob = problem(lp)
+    assert prob.panels() == (0, 0)
+    prob.close()

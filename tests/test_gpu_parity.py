@@ -139,12 +139,12 @@ def test_skewed_rows_match_oracle_over_restarts():
 
 
 def test_trajectory_long_rows_block_reduction():
-    """Rows longer than the LDS stage (4096 nonzeros) take the block-wide
-    reduction path of the row-block SpMV; rows between 2048 and 4096 are
-    staged alone; short rows share blocks."""
+    """Rows longer than 64 nonzeros (up to 9,000, beyond the LDS stage and the
+    2048-nonzero chunk) stand alone and take the block-wide reduction of the
+    row-block SpMV; short rows share staged blocks."""
     lp = lpgen.gen(3000, 20000, zipf_alpha=1.3, cap=9000, eq_frac=0.3, free_frac=0.2, values="normal", seed=7)
     lens = np.diff(lp.A.indptr)
-    assert (lens > 4096).sum() > 100 and ((lens > 2048) & (lens <= 4096)).sum() > 10
+    assert (lens > 4096).sum() > 100 and ((lens > 64) & (lens <= 2048)).sum() > 100
     announce(f"trajectory long rows nnz={lp.nnz} max_row={lp.meta['max_row']}")
     out, ref, worst = _trajectory_case(lp, T=100, max_iter=200)
     assert out["info"]["restarts"] == ref.restarts
