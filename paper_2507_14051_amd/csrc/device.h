@@ -76,15 +76,20 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NQV], double* out
 }
 
 // ---------------------------------------------------------------- row blocks
-// The hot SpMVs walk "row blocks" built at setup: each block covers at most
-// kRbRows consecutive rows whose nonzeros start in the same kRbCap-sized chunk
-// of the value array, and a row longer than kRbSerial forms a block of its own.
-// So a block of several rows holds at most kRbCap + kRbSerial = kRbLds
-// nonzeros, staged in LDS and summed per row by one thread (at most kRbSerial
-// terms); a single-row block is reduced by the whole block.
+// The hot SpMVs walk "row blocks" built at setup.  A row is short (at most
+// kRbSerial nonzeros), medium (at most kRbMed) or long.  A block holds
+//  - up to kRbRows consecutive short rows whose nonzeros start in the same
+//    kRbCap-sized chunk (so at most kRbCap + kRbSerial = kRbLds nonzeros):
+//    products staged in LDS, each row summed by its own thread;
+//  - or up to kWaves consecutive medium rows inside an aligned group of
+//    kWaves rows: one wave per row, a fixed shuffle tree per wave;
+//  - or one row (a long one, or a row cut off by the rules above): strided
+//    partials over the whole block, a fixed shuffle tree, the waves in order.
+// The kind is decided from the block's row and nonzero counts alone.
 constexpr int kRbRows = kBlock;
 constexpr int kRbCap = 2048;
 constexpr int kRbSerial = 64;
+constexpr int kRbMed = 1024;
 constexpr int kRbLds = kRbCap + kRbSerial;
 
 template <typename T>
@@ -99,15 +104,10 @@ __device__ __forceinline__ T block_sum_to0(T v) {
   return r;  // every thread gets the block sum
 }
 
-// Row sums of val .* vec[idx] over the calling block's rows [s, e) with
-// nonzeros [ps, pe).  In a block of several rows thread t returns the sum of
-// row s + t (products staged in LDS, then summed left to right); in a
-// single-row block (single = e - s == 1) every thread returns that row's sum
-// (strided partials, a fixed shuffle tree and the waves in order).
-// Deterministic either way.
-// Each thread handles the nonzeros ps + tid + k*kBlock in batches of kRbUnroll:
-// all index and value loads of a batch are issued, then all gathers, then the
-// products, so a thread has a whole batch of gathers in flight instead of one.
+// Each lane handles the nonzeros first + lane + k*STRIDE of [first, end) in
+// batches of kRbUnroll: all index and value loads of a batch are issued, then
+// all gathers, then the products, so a lane has a whole batch of gathers in
+// flight instead of one.
 constexpr int kRbUnroll = 8;
 
 // NT: load the matrix arrays (idx, val) as streaming (non-temporal) data so a
@@ -118,21 +118,20 @@ __device__ __forceinline__ T ld(const T* p) {
   else return *p;
 }
 
-template <typename ACC, bool NT = false, typename V, typename X>
-__device__ __forceinline__ ACC rb_dot(const int32_t* __restrict__ idx, const V* __restrict__ val,
-                                      const X* __restrict__ vec, int ps, int pe, int a0, int a1,
-                                      bool own, bool single, ACC* lds) {
-  const int tid = threadIdx.x;
-  const bool staged = !single;  // block-uniform; several rows imply pe - ps <= kRbLds
+// STAGE: write each product to lds[q - first] instead of summing.
+template <int STRIDE, bool STAGE, bool NT, typename ACC, typename V, typename X>
+__device__ __forceinline__ ACC strided_products(const int32_t* __restrict__ idx, const V* __restrict__ val,
+                                                const X* __restrict__ vec, int first, int end, int lane,
+                                                ACC* lds) {
   ACC part = 0;
-  for (int base = ps + tid; base < pe; base += kBlock * kRbUnroll) {
+  for (int base = first + lane; base < end; base += STRIDE * kRbUnroll) {
     // Past the end, the clamped position repeats the last nonzero (a valid
     // address, so the loads need no branch) and its product is dropped.
     int ix[kRbUnroll];
     V vv[kRbUnroll];
 #pragma unroll
     for (int u = 0; u < kRbUnroll; ++u) {
-      const int q = min(base + u * kBlock, pe - 1);
+      const int q = min(base + u * STRIDE, end - 1);
       ix[u] = ld<NT>(idx + q);
       vv[u] = ld<NT>(val + q);
     }
@@ -141,24 +140,53 @@ __device__ __forceinline__ ACC rb_dot(const int32_t* __restrict__ idx, const V* 
     for (int u = 0; u < kRbUnroll; ++u) g[u] = vec[ix[u]];
 #pragma unroll
     for (int u = 0; u < kRbUnroll; ++u) {
-      const ACC prod = base + u * kBlock < pe ? (ACC)vv[u] * (ACC)g[u] : ACC(0);
-      if (staged) {
-        const int q = base + u * kBlock;
-        if (q < pe) lds[q - ps] = prod;
+      const int q = base + u * STRIDE;
+      const ACC prod = q < end ? (ACC)vv[u] * (ACC)g[u] : ACC(0);
+      if constexpr (STAGE) {
+        if (q < end) lds[q - first] = prod;
       } else {
         part += prod;
       }
     }
   }
-  if (staged) {
+  return part;
+}
+
+// Row sums of val .* vec[idx] over the calling block's nrows rows with
+// nonzeros [ps, pe); thread t (own: t < nrows) holds the pointers [a0, a1) of
+// its row and gets that row's sum (in a single-row block every thread gets
+// it).  Deterministic in every kind of block.
+template <typename ACC, bool NT = false, typename V, typename X>
+__device__ __forceinline__ ACC rb_dot(const int32_t* __restrict__ idx, const V* __restrict__ val,
+                                      const X* __restrict__ vec, int ps, int pe, int a0, int a1,
+                                      bool own, int nrows, ACC* lds) {
+  const int tid = threadIdx.x;
+  if (nrows == 1)
+    return block_sum_to0(strided_products<kBlock, false, NT, ACC>(idx, val, vec, ps, pe, tid, lds));
+  if (pe - ps > nrows * kRbSerial) {  // medium rows (a block of short rows has at most kRbSerial per row)
+    __shared__ int sh_ptr[kWaves + 1];
+    __shared__ ACC sh_sum[kWaves];
+    if (own) {
+      sh_ptr[tid] = a0;
+      if (tid == nrows - 1) sh_ptr[nrows] = a1;
+    }
     __syncthreads();
-    ACC acc = 0;
-    if (own)
-      for (int q = a0 - ps; q < a1 - ps; ++q) acc += lds[q];
+    const int w = tid >> 6;
+    if (w < nrows) {
+      const ACC part = strided_products<64, false, NT, ACC>(idx, val, vec, sh_ptr[w], sh_ptr[w + 1], tid & 63, lds);
+      const ACC sum = wave_sum(part);
+      if ((tid & 63) == 0) sh_sum[w] = sum;
+    }
     __syncthreads();
-    return acc;
+    return own ? sh_sum[tid] : ACC(0);
   }
-  return block_sum_to0(part);
+  strided_products<kBlock, true, NT, ACC>(idx, val, vec, ps, pe, tid, lds);
+  __syncthreads();
+  ACC acc = 0;
+  if (own)
+    for (int q = a0 - ps; q < a1 - ps; ++q) acc += lds[q];
+  __syncthreads();
+  return acc;
 }
 
 }  // namespace hlp

@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_cols(ColArgs p) {
     a0 = p.cp[j]; a1 = p.cp[j + 1];
     gn = p.gxn[j]; ga = p.gxa[j]; c = p.code[j];
   }
-  const double acc = rb_dot<double>(p.row, p.tval, p.gw, p.cp[s], p.cp[e], a0, a1, own, e - s == 1, lds);
+  const double acc = rb_dot<double>(p.row, p.tval, p.gw, p.cp[s], p.cp[e], a0, a1, own, e - s, lds);
   if (!own) return;
   double gxh, gin = 0.0;
   if (p.mode == MODE_LAST) {
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_rows(RowArgs p) {
     a0 = p.rp[i]; a1 = p.rp[i + 1];
     pyi = p.prev.py[i];
   }
-  const double acc = rb_dot<double>(p.col, p.val, p.u, p.rp[s], p.rp[e], a0, a1, own, e - s == 1, lds);
+  const double acc = rb_dot<double>(p.col, p.val, p.u, p.rp[s], p.rp[e], a0, a1, own, e - s, lds);
   if (!own) return;
   const double gyin = pyi + acc;
   p.prev.gyn[i] = gyin;

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kBlock) void k_primal(PrimalArgs p) {
     xj = p.x[j]; cj = p.ct[j]; lo = p.lv[j]; hi = p.uv[j]; xaj = p.xa[j];
     a0 = p.cp[j]; a1 = p.cp[j + 1];
   }
-  const double g = rb_dot<double, NT>(p.row, p.tval, p.y, ps, pe, a0, a1, own, e - s == 1, lds);
+  const double g = rb_dot<double, NT>(p.row, p.tval, p.y, ps, pe, a0, a1, own, e - s, lds);
   double q0 = 0.0, q1 = 0.0;
   if (own) {
     const double tau = p.step->tau, gam = p.step->gamma, a = halpern_a(p.step, p.j);
@@ -124,11 +124,11 @@ __global__ __launch_bounds__(kBlock) void k_dual(DualArgs p) {
     if (RES) dri = p.dr[i];
     a0 = p.rp[i]; a1 = p.rp[i + 1];
   }
-  const double h = rb_dot<double, NT>(p.col, p.val, p.xbar, ps, pe, a0, a1, own, e - s == 1, lds);
+  const double h = rb_dot<double, NT>(p.col, p.val, p.xbar, ps, pe, a0, a1, own, e - s, lds);
   double adx = 0.0, axh = 0.0;
   if (RES) {
-    adx = rb_dot<double>(p.col, p.val, p.dx, ps, pe, a0, a1, own, e - s == 1, lds);
-    axh = rb_dot<double>(p.col, p.val, p.xh, ps, pe, a0, a1, own, e - s == 1, lds);
+    adx = rb_dot<double>(p.col, p.val, p.dx, ps, pe, a0, a1, own, e - s, lds);
+    axh = rb_dot<double>(p.col, p.val, p.xh, ps, pe, a0, a1, own, e - s, lds);
   }
   double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (own) {
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void k_panel_dot(PanelDotArgs<T> p) {
   const bool own = r < blk.y;
   int a0 = 0, a1 = 0;
   if (own) { a0 = p.pp[r]; a1 = p.pp[r + 1]; }
-  const T acc = rb_dot<T, NT>(p.pcol, p.pval, p.vec, blk.z, blk.w, a0, a1, own, blk.y - blk.x == 1, lds);
+  const T acc = rb_dot<T, NT>(p.pcol, p.pval, p.vec, blk.z, blk.w, a0, a1, own, blk.y - blk.x, lds);
   if (own) p.out[r] = acc;
 }
 
@@ -199,6 +199,9 @@ __device__ __forceinline__ T panel_sum(const T* __restrict__ part, int32_t P, in
 __device__ __forceinline__ bool is_long(const uint32_t* __restrict__ bits, int i) {
   return (bits[i >> 5] >> (i & 31)) & 1u;
 }
+
+// The host sizes the long-row part of the grid as ceil(nL / 256).
+static_assert(kBlock == 256, "k_dual_pn: one long row per thread of 256-thread blocks");
 
 struct DualPanelArgs {
   const int4* rb; const int32_t* sp; const int32_t* scol; const double* sval; const double* xbar;
@@ -223,7 +226,7 @@ __global__ __launch_bounds__(kBlock) void k_dual_pn(DualPanelArgs p) {
       own = !is_long(p.lbits, i);
       if (own) { yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i]; }
     }
-    h = rb_dot<double, NT>(p.scol, p.sval, p.xbar, blk.z, blk.w, a0, a1, in, blk.y - blk.x == 1, lds);
+    h = rb_dot<double, NT>(p.scol, p.sval, p.xbar, blk.z, blk.w, a0, a1, in, blk.y - blk.x, lds);
   } else {
     const int l = ((int)blockIdx.x - p.nbS) * kBlock + threadIdx.x;
     own = l < p.nL;
@@ -264,7 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_dual32_pn(Dual32PanelArgs p) {
       own = !is_long(p.lbits, i);
       if (own) { yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i]; bi = p.b[i]; }
     }
-    h = rb_dot<float, NT>(p.scol, p.sval, p.xbar, blk.z, blk.w, a0, a1, in, blk.y - blk.x == 1, lds);
+    h = rb_dot<float, NT>(p.scol, p.sval, p.xbar, blk.z, blk.w, a0, a1, in, blk.y - blk.x, lds);
   } else {
     const int l = ((int)blockIdx.x - p.nbS) * kBlock + threadIdx.x;
     own = l < p.nL;
@@ -303,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_kkt_cols(KktColArgs p) {
     a0 = p.cp[j];
     a1 = p.cp[j + 1];
   }
-  const double acc = rb_dot<double>(p.row, p.tval, p.yh, p.cp[s], p.cp[e], a0, a1, own, e - s == 1, lds);
+  const double acc = rb_dot<double>(p.row, p.tval, p.yh, p.cp[s], p.cp[e], a0, a1, own, e - s, lds);
   double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (own) {
     const double g = p.ct[j] - acc;
@@ -350,7 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_kkt_rows(KktRowArgs p) {
     a0 = p.rp[i];
     a1 = p.rp[i + 1];
   }
-  const double acc = rb_dot<double>(p.col, p.val, p.xh, p.rp[s], p.rp[e], a0, a1, own, e - s == 1, lds);
+  const double acc = rb_dot<double>(p.col, p.val, p.xh, p.rp[s], p.rp[e], a0, a1, own, e - s, lds);
   double q[3] = {0.0, 0.0, 0.0};
   if (own) {
     const double lo = p.lc[i], hi = p.uc[i];
@@ -390,7 +393,7 @@ __global__ __launch_bounds__(kBlock) void k_primal32(Primal32Args p) {
     xj = p.x[j]; cj = p.c[j]; lo = p.lv[j]; hi = p.uv[j]; xaj = p.xa[j];
     a0 = p.cp[j]; a1 = p.cp[j + 1];
   }
-  const float g = rb_dot<float, NT>(p.row, p.tval, p.y, ps, pe, a0, a1, own, e - s == 1, lds);
+  const float g = rb_dot<float, NT>(p.row, p.tval, p.y, ps, pe, a0, a1, own, e - s, lds);
   double q0 = 0.0, q1 = 0.0;
   if (own) {
     const float tau = (float)p.step->tau, gam = (float)p.step->gamma, a = (float)halpern_a(p.step, p.j);
@@ -434,9 +437,9 @@ __global__ __launch_bounds__(kBlock) void k_dual32(Dual32Args p) {
     yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i]; bi = p.b[i];
     a0 = p.rp[i]; a1 = p.rp[i + 1];
   }
-  const float h = rb_dot<float, NT>(p.col, p.val, p.xbar, ps, pe, a0, a1, own, e - s == 1, reinterpret_cast<float*>(lds));
+  const float h = rb_dot<float, NT>(p.col, p.val, p.xbar, ps, pe, a0, a1, own, e - s, reinterpret_cast<float*>(lds));
   double adx = 0.0;
-  if (RES) adx = rb_dot<double>(p.col, p.val, p.dx, ps, pe, a0, a1, own, e - s == 1, lds);
+  if (RES) adx = rb_dot<double>(p.col, p.val, p.dx, ps, pe, a0, a1, own, e - s, lds);
   double q[3] = {0.0, 0.0, 0.0};
   if (own) {
     const float sigma = (float)p.step->sigma, gam = (float)p.step->gamma, a = (float)halpern_a(p.step, p.j);

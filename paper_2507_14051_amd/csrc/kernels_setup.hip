@@ -256,10 +256,14 @@ __global__ void k_gather_transpose(const int32_t* __restrict__ perm, const int32
 }
 
 // ----------------------------------------------------------------- row blocks
+// Row kind: 0 short (at most kRbSerial nonzeros), 1 medium (at most kRbMed), 2 long.
+__device__ __forceinline__ int row_kind(int len) { return len > kRbMed ? 2 : (len > kRbSerial ? 1 : 0); }
+
 // Row r starts a block if r is a multiple of kRbRows, if its nonzeros start in
-// another kRbCap-sized chunk than those of row r-1, or if row r or row r-1 is
-// longer than kRbSerial (such rows stand alone); with period > 0 also every
-// period-th row (the first row of each column panel).
+// another kRbCap-sized chunk than those of row r-1, if its kind differs from
+// that of row r-1, if it is long (long rows stand alone), or if it is medium
+// and r is a multiple of kWaves (medium rows go kWaves to a block at most);
+// with period > 0 also every period-th row (the first row of each column panel).
 __global__ void k_rb_flags(const int32_t* __restrict__ ptr, int32_t rows, int32_t period,
                            int32_t* __restrict__ flags) {
   int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -267,8 +271,9 @@ __global__ void k_rb_flags(const int32_t* __restrict__ ptr, int32_t rows, int32_
   int f = 1;
   if (r > 0) {
     const int p0 = ptr[r - 1], p1 = ptr[r], p2 = ptr[r + 1];
-    f = (r % kRbRows == 0) || (p1 / kRbCap != p0 / kRbCap) || (p1 - p0 > kRbSerial) ||
-        (p2 - p1 > kRbSerial) || (period > 0 && r % period == 0);
+    const int k0 = row_kind(p1 - p0), k1 = row_kind(p2 - p1);
+    f = (r % kRbRows == 0) || (p1 / kRbCap != p0 / kRbCap) || (k1 != k0) || (k1 == 2) ||
+        (k1 == 1 && r % kWaves == 0) || (period > 0 && r % period == 0);
   }
   flags[r] = f;
 }
@@ -515,7 +520,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_plain(const int32_t* __restrict
     a0 = ptr[i];
     a1 = ptr[i + 1];
   }
-  const double v = rb_dot<double>(idx, val, x, ptr[s], ptr[e], a0, a1, own, e - s == 1, lds);
+  const double v = rb_dot<double>(idx, val, x, ptr[s], ptr[e], a0, a1, own, e - s, lds);
   double q[1] = {0.0};
   if (own) {
     out[i] = v;
