@@ -112,7 +112,10 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
   L->xh = c.take<double>(n);
   L->dxv = c.take<double>(n);
   L->rbuf = c.take<double>(n);
-  L->y = c.take<double>(m);
+  // with column panels, y (and y32) carry a compact copy of the long rows'
+  // entries after the m entries: y[m + l] = y[lrow[l]]
+  const int64_t ycopy = panels > 0 ? nLmax : 0;
+  L->y = c.take<double>(m + ycopy);
   L->ya = c.take<double>(m);
   L->yh = c.take<double>(m);
   if (mixed) {
@@ -124,7 +127,7 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
     L->c32 = c.take<float>(n);
     L->lv32 = c.take<float>(n);
     L->uv32 = c.take<float>(n);
-    L->y32 = c.take<float>(m);
+    L->y32 = c.take<float>(m + ycopy);
     L->ya32 = c.take<float>(m);
     L->yh32 = c.take<float>(m);
     L->lc32 = c.take<float>(m);
@@ -179,6 +182,7 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
     L->rbP = c.take<int32_t>(R + 2);
     L->rbxP = c.take<int32_t>(4 * (R + 1));
     L->tabP = c.take<int32_t>(4 * (R + 1));
+    L->rowc = c.take<int32_t>(nnz);
     L->pscrA = c.take<int32_t>(std::max<int64_t>(m, R) + 1);
     L->pscrB = c.take<int32_t>(std::max<int64_t>(m, R) + 1);
   }
@@ -284,6 +288,7 @@ static hlp_err build_panels(hlp_lp* lp, int32_t P, int32_t T, bool automatic) {
   HLP_HIP(hipStreamSynchronize(lp->stream));
   lp->nbS = cnt[2];
   lp->nbP = cnt[3];
+  HLP_HIP(launch_panel_remap(lp));
   // blocks of panel p: [pstart[p], pstart[p+1]); dealt to XCD p mod 8 in panel order
   std::vector<int32_t> pstart(P + 1);
   HLP_HIP(launch_panel_starts(lp, lp->pscrA));

@@ -103,6 +103,16 @@ double fixed_point_residual(const double* R, double eta, double omega) {
   return std::sqrt(std::max(q, 0.0));
 }
 
+// The reverse mode recomputes each segment with the unsplit dual half-step;
+// the forward pass uses the same kernels, so the column-panel layout is
+// switched off while either runs (its summation order differs).
+struct PanelsOff {
+  hlp_lp* lp;
+  int32_t saved;
+  explicit PanelsOff(hlp_lp* l) : lp(l), saved(l->panels) { l->panels = 0; }
+  ~PanelsOff() { lp->panels = saved; }
+};
+
 }  // namespace
 
 }  // namespace hlp
@@ -162,6 +172,7 @@ hlp_err hlp_unrolled_forward(hlp_lp* lp, const hlp_params* pp, int32_t K, int32_
   }
   const double eta = lp->eta;
   StepTracker steps{eta};
+  PanelsOff unsplit(lp);
   HLP_HIP(launch_warm_start(lp, x0, y0));
   double om = p.omega0;
   int64_t k = 0;
@@ -282,6 +293,7 @@ hlp_err hlp_unrolled_backward(hlp_lp* lp, const void* tape, size_t tape_bytes, c
   HLP_HIP(hipStreamSynchronize(lp->stream));
   const double eta = h.eta, gamma = h.gamma;
   StepTracker steps{eta};
+  PanelsOff unsplit(lp);
   const AdjVecs v = adj_vecs(base, L, n, m);
   HLP_HIP(launch_zero_adj(lp, v));
   uint8_t* masks = reinterpret_cast<uint8_t*>(base + L.masks);

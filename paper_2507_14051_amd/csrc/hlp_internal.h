@@ -95,6 +95,9 @@ struct hlp_lp {
   double* pval = nullptr;
   float* pval32 = nullptr;
   double* ppart = nullptr;            // partial row sums, P*nL (float in the FP32 path)
+  // A~^T's row indices with the long rows redirected to the compact copy of
+  // their y entries (index m + l); gathered by the plain primal half-steps
+  int32_t* rowc = nullptr;
   int32_t *rbS = nullptr, *rbxS = nullptr, *rbP = nullptr, *rbxP = nullptr, *tabP = nullptr;
   int32_t *pscrA = nullptr, *pscrB = nullptr;  // setup scratch
   int32_t nbS = 0, nbP = 0, nbPgrid = 0, nbC = 0;
@@ -197,6 +200,7 @@ hipError_t launch_build_row_blocks(hlp_lp* lp, const int32_t* ptr, int32_t rows,
 hipError_t launch_panel_split(hlp_lp* lp, int32_t T, int32_t* counts);
 hipError_t launch_panel_layout(hlp_lp* lp, int32_t* counts);
 hipError_t launch_panel_starts(hlp_lp* lp, int32_t* pstart);
+hipError_t launch_panel_remap(hlp_lp* lp);
 hipError_t launch_set_step(hlp_lp* lp, double tau, double sigma, double gamma, int64_t k0, double P = 1.0,
                            double D = 1.0);
 hipError_t launch_primal(hlp_lp* lp, const StepArgs& s);

@@ -156,6 +156,13 @@ __global__ __launch_bounds__(kBlock) void k_dual(DualArgs p) {
 }
 
 // ---------------------------------------------------------------------------- column panels
+// y[m + l] <- y[lrow[l]]: the compact copy of the long rows' entries.
+template <typename T>
+__global__ void k_refresh_long_y(T* __restrict__ y, const int32_t* __restrict__ lrow, int32_t nL, int32_t m) {
+  const int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (l < nL) y[m + l] = y[lrow[l]];
+}
+
 // Dual half-step with the long rows split into column panels (plain
 // iterations only).  k_panel_dot reduces each (panel, long row) segment; the
 // blocks of panel p run on XCD p mod 8 (workgroups are dealt to the XCDs in
@@ -207,13 +214,13 @@ struct DualPanelArgs {
   const int4* rb; const int32_t* sp; const int32_t* scol; const double* sval; const double* xbar;
   double* y; const double* ya; const double* lc; const double* uc; const StepDev* step;
   const uint32_t* lbits; const int32_t* lrow; const double* part;
-  int32_t P, nL, nbS, j;
+  int32_t P, nL, nbS, j, m;
 };
 
 template <bool NT>
 __global__ __launch_bounds__(kBlock) void k_dual_pn(DualPanelArgs p) {
   __shared__ double lds[kRbLds];
-  int i = 0;
+  int i = 0, l = -1;
   bool own = false;
   double h = 0.0, yi = 0.0, lo = 0.0, hi = 0.0, yai = 0.0;
   if ((int)blockIdx.x < p.nbS) {
@@ -228,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void k_dual_pn(DualPanelArgs p) {
     }
     h = rb_dot<double, NT>(p.scol, p.sval, p.xbar, blk.z, blk.w, a0, a1, in, blk.y - blk.x, lds);
   } else {
-    const int l = ((int)blockIdx.x - p.nbS) * kBlock + threadIdx.x;
+    l = ((int)blockIdx.x - p.nbS) * kBlock + threadIdx.x;
     own = l < p.nL;
     if (own) {
       i = p.lrow[l];
@@ -240,7 +247,9 @@ __global__ __launch_bounds__(kBlock) void k_dual_pn(DualPanelArgs p) {
     const double sigma = p.step->sigma, gam = p.step->gamma, a = halpern_a(p.step, p.j);
     const double w = h - yi / sigma;
     const double yh = sigma * (clampv(w, lo, hi) - w);
-    p.y[i] = a * ((1.0 + gam) * yh - gam * yi) + (1.0 - a) * yai;
+    const double yn = a * ((1.0 + gam) * yh - gam * yi) + (1.0 - a) * yai;
+    p.y[i] = yn;
+    if (l >= 0) p.y[p.m + l] = yn;  // the compact copy gathered by the primal half-step
   }
 }
 
@@ -248,13 +257,13 @@ struct Dual32PanelArgs {
   const int4* rb; const int32_t* sp; const int32_t* scol; const float* sval; const float* xbar;
   float* y; const float* ya; const float* lc; const float* uc; const float* b; const StepDev* step;
   const uint32_t* lbits; const int32_t* lrow; const float* part;
-  int32_t P, nL, nbS, j;
+  int32_t P, nL, nbS, j, m;
 };
 
 template <bool NT>
 __global__ __launch_bounds__(kBlock) void k_dual32_pn(Dual32PanelArgs p) {
   __shared__ float lds[kRbLds];
-  int i = 0;
+  int i = 0, l = -1;
   bool own = false;
   float h = 0.0f, yi = 0.0f, lo = 0.0f, hi = 0.0f, yai = 0.0f, bi = 0.0f;
   if ((int)blockIdx.x < p.nbS) {
@@ -269,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_dual32_pn(Dual32PanelArgs p) {
     }
     h = rb_dot<float, NT>(p.scol, p.sval, p.xbar, blk.z, blk.w, a0, a1, in, blk.y - blk.x, lds);
   } else {
-    const int l = ((int)blockIdx.x - p.nbS) * kBlock + threadIdx.x;
+    l = ((int)blockIdx.x - p.nbS) * kBlock + threadIdx.x;
     own = l < p.nL;
     if (own) {
       i = p.lrow[l];
@@ -281,7 +290,9 @@ __global__ __launch_bounds__(kBlock) void k_dual32_pn(Dual32PanelArgs p) {
     const float sigma = (float)p.step->sigma, gam = (float)p.step->gamma, a = (float)halpern_a(p.step, p.j);
     const float w = h - (bi + yi) / sigma;
     const float yh = yi + sigma * (clampv(w, lo, hi) - h);
-    p.y[i] = a * ((1.0f + gam) * yh - gam * yi) + (1.0f - a) * yai;
+    const float yn = a * ((1.0f + gam) * yh - gam * yi) + (1.0f - a) * yai;
+    p.y[i] = yn;
+    if (l >= 0) p.y[p.m + l] = yn;
   }
 }
 
@@ -634,6 +645,14 @@ hipError_t launch_panel_pair(hlp_lp* lp, const T* pval, const T* vec, KD kdual, 
   return launch_step_kernel(kdual, lp->nbS + lp->nbC, s2, lp->stream, ad);
 }
 
+template <typename T>
+hipError_t refresh_long_y(hlp_lp* lp, T* y) {
+  if (!lp->panels || lp->nL == 0 || !y) return hipSuccess;
+  hipLaunchKernelGGL(k_refresh_long_y<T>, dim3(nblocks(lp->nL)), dim3(kBlock), 0, lp->stream, y, lp->lrow, lp->nL,
+                     lp->m);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 // ============================================================================ launchers
@@ -648,6 +667,7 @@ hipError_t launch_primal(hlp_lp* lp, const StepArgs& s) {
                lp->xbar, lp->xh, lp->dxv, region(lp, R_PRIMAL), s.mask_x, lp->step, s.j};
   if (s.mask_x) return launch_step_kernel(k_primal<2, false>, lp->nbT, s, lp->stream, a);
   if (s.residual) return launch_step_kernel(k_primal<1, false>, lp->nbT, s, lp->stream, a);
+  if (lp->panels) a.row = lp->rowc;  // long rows' y entries from the compact copy
   if (lp->nt) return launch_step_kernel(k_primal<0, true>, lp->nbT, s, lp->stream, a);
   return launch_step_kernel(k_primal<0, false>, lp->nbT, s, lp->stream, a);
 }
@@ -656,11 +676,15 @@ hipError_t launch_dual(hlp_lp* lp, const StepArgs& s) {
   if (lp->nbA == 0) return hipSuccess;
   DualArgs a{reinterpret_cast<const int4*>(lp->rbxA), lp->rp, lp->col, lp->val, lp->xbar, lp->dxv, lp->xh, lp->y, lp->ya, lp->lct, lp->uct,
              lp->dr, lp->yh, region(lp, R_DUAL), s.mask_y, lp->step, s.j};
-  if (s.mask_y) return launch_step_kernel(k_dual<2, false>, lp->nbA, s, lp->stream, a);
-  if (s.residual) return launch_step_kernel(k_dual<1, false>, lp->nbA, s, lp->stream, a);
+  if (s.mask_y || s.residual) {
+    hipError_t e = s.mask_y ? launch_step_kernel(k_dual<2, false>, lp->nbA, s, lp->stream, a)
+                            : launch_step_kernel(k_dual<1, false>, lp->nbA, s, lp->stream, a);
+    return e != hipSuccess ? e : refresh_long_y(lp, lp->y);
+  }
   if (lp->panels) {
     DualPanelArgs d{reinterpret_cast<const int4*>(lp->rbxS), lp->sp, lp->scol, lp->sval, lp->xbar, lp->y, lp->ya,
-                    lp->lct, lp->uct, lp->step, lp->lbits, lp->lrow, lp->ppart, lp->panels, lp->nL, lp->nbS, s.j};
+                    lp->lct, lp->uct, lp->step, lp->lbits, lp->lrow, lp->ppart, lp->panels, lp->nL, lp->nbS, s.j,
+                    lp->m};
     return lp->nt ? launch_panel_pair<double>(lp, lp->pval, lp->xbar, k_dual_pn<true>, d, s)
                   : launch_panel_pair<double>(lp, lp->pval, lp->xbar, k_dual_pn<false>, d, s);
   }
@@ -714,7 +738,8 @@ hipError_t launch_restart_copy(hlp_lp* lp, int32_t to_current) {
   if (N == 0) return hipSuccess;
   hipLaunchKernelGGL(k_restart_copy, dim3(nblocks(N)), dim3(kBlock), 0, lp->stream, lp->x, lp->xa, lp->xh,
                      lp->y, lp->ya, lp->yh, lp->n, lp->m, to_current);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : refresh_long_y(lp, lp->y);
 }
 
 hipError_t launch_warm_start(hlp_lp* lp, const double* x0, const double* y0) {
@@ -722,7 +747,8 @@ hipError_t launch_warm_start(hlp_lp* lp, const double* x0, const double* y0) {
   if (N == 0) return hipSuccess;
   hipLaunchKernelGGL(k_warm_start, dim3(nblocks(N)), dim3(kBlock), 0, lp->stream, x0, y0, lp->dr, lp->dc,
                      lp->x, lp->xa, lp->y, lp->ya, lp->n, lp->m);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : refresh_long_y(lp, lp->y);
 }
 
 hipError_t launch_unscale(hlp_lp* lp, double* x, double* y) {
@@ -760,6 +786,7 @@ hipError_t launch_primal32(hlp_lp* lp, const StepArgs& s) {
   Primal32Args a{reinterpret_cast<const int4*>(lp->rbxT), lp->cp, lp->row, lp->tval32, lp->y32, lp->x32, lp->xa32, lp->c32, lp->lv32, lp->uv32,
                  lp->xbar32, lp->xh32, lp->dx32, region(lp, R_PRIMAL), lp->step, s.j};
   if (s.residual) return launch_step_kernel(k_primal32<true, false>, lp->nbT, s, lp->stream, a);
+  if (lp->panels) a.row = lp->rowc;
   if (lp->nt) return launch_step_kernel(k_primal32<false, true>, lp->nbT, s, lp->stream, a);
   return launch_step_kernel(k_primal32<false, false>, lp->nbT, s, lp->stream, a);
 }
@@ -768,12 +795,15 @@ hipError_t launch_dual32(hlp_lp* lp, const StepArgs& s) {
   if (lp->nbA == 0) return hipSuccess;
   Dual32Args a{reinterpret_cast<const int4*>(lp->rbxA), lp->rp, lp->col, lp->val32, lp->xbar32, lp->dx32, lp->y32, lp->ya32, lp->lc32, lp->uc32,
                lp->b32, lp->yh32, region(lp, R_DUAL), lp->step, s.j};
-  if (s.residual) return launch_step_kernel(k_dual32<true, false>, lp->nbA, s, lp->stream, a);
+  if (s.residual) {
+    hipError_t e = launch_step_kernel(k_dual32<true, false>, lp->nbA, s, lp->stream, a);
+    return e != hipSuccess ? e : refresh_long_y(lp, lp->y32);
+  }
   if (lp->panels) {
     const float* part = reinterpret_cast<const float*>(lp->ppart);
     Dual32PanelArgs d{reinterpret_cast<const int4*>(lp->rbxS), lp->sp, lp->scol, lp->sval32, lp->xbar32, lp->y32,
                       lp->ya32, lp->lc32, lp->uc32, lp->b32, lp->step, lp->lbits, lp->lrow, part, lp->panels, lp->nL,
-                      lp->nbS, s.j};
+                      lp->nbS, s.j, lp->m};
     return lp->nt ? launch_panel_pair<float>(lp, lp->pval32, lp->xbar32, k_dual32_pn<true>, d, s)
                   : launch_panel_pair<float>(lp, lp->pval32, lp->xbar32, k_dual32_pn<false>, d, s);
   }
@@ -796,7 +826,8 @@ hipError_t launch_recentre(hlp_lp* lp, double P, double D) {
                      lp->atyc, lp->ct, lp->lvt, lp->uvt, lp->lct, lp->uct, P, D, lp->xcen, lp->ycen, lp->c32,
                      lp->lv32, lp->uv32, lp->lc32, lp->uc32, lp->b32, lp->x32, lp->xa32, lp->y32, lp->ya32,
                      lp->n, lp->m);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : refresh_long_y(lp, lp->y32);
 }
 
 }  // namespace hlp

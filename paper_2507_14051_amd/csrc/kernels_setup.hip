@@ -407,6 +407,15 @@ __global__ void k_pn_long(const int32_t* __restrict__ rp, const int32_t* __restr
   }
 }
 
+__global__ void k_pn_remap(const int32_t* __restrict__ row, const int32_t* __restrict__ plid, int32_t m,
+                           int64_t nnz, int32_t* __restrict__ rowc) {
+  int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= nnz) return;
+  const int i = row[q];
+  const int l = plid[i];
+  rowc[q] = plid[i + 1] != l ? m + l : i;
+}
+
 // First block of each panel (panels start blocks: see k_rb_flags).
 __global__ void k_pn_starts(const int32_t* __restrict__ rbx, int32_t nb, int32_t nL, int32_t* __restrict__ pstart) {
   int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -776,6 +785,13 @@ hipError_t launch_panel_layout(hlp_lp* lp, int32_t* counts) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = launch_build_row_blocks(lp, lp->sp, m, lp->rbS, lp->rbxS, counts + 2)) != hipSuccess) return e;
   return launch_build_row_blocks(lp, lp->pp, (int32_t)R, lp->rbP, lp->rbxP, counts + 3, nL);
+}
+
+hipError_t launch_panel_remap(hlp_lp* lp) {
+  if (lp->nnz == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pn_remap, dim3(nblocks(lp->nnz)), dim3(kBlock), 0, lp->stream, lp->row, lp->plid, lp->m,
+                     lp->nnz, lp->rowc);
+  return hipGetLastError();
 }
 
 hipError_t launch_panel_starts(hlp_lp* lp, int32_t* pstart) {

@@ -180,3 +180,28 @@ def test_panels_off_by_default_on_small_lp():
     prob = problem(lp)
     assert prob.panels() == (0, 0)
     prob.close()
+
+
+def test_panels_leave_adjoint_and_later_solves_unchanged():
+    """The unrolled forward/reverse pass runs with the unsplit dual step (the
+    panel layout is switched off inside it), so its outputs and gradients are
+    bitwise those of a handle without panels; a solve after it still keeps
+    the compact copy of the long rows' y entries (same end point as before)."""
+    from tests.test_gpu_adjoint import KEYS, _grads
+    lp = lpgen.gen(800, 3000, zipf_alpha=1.4, cap=2500, eq_frac=0.3, free_frac=0.2, values="normal", seed=4)
+    announce(f"panels adjoint nnz={lp.nnz}")
+    rng = np.random.default_rng(4)
+    gx = rng.standard_normal(lp.n); gy = rng.standard_normal(lp.m)
+    pa = problem(lp, column_panels=8, panel_row_min=8)
+    assert pa.panels()[0] == 8
+    before = np_out(pa.solve(tol=0.0, max_iter=150))
+    xa, ya, ga = _grads(pa, lp, 120, 25, gx, gy, eval_freq=16)
+    after = np_out(pa.solve(tol=0.0, max_iter=150))
+    pa.close()
+    pb = problem(lp, column_panels=0)
+    xb, yb, gb = _grads(pb, lp, 120, 25, gx, gy, eval_freq=16)
+    pb.close()
+    assert np.array_equal(xa, xb) and np.array_equal(ya, yb)
+    for k in KEYS:
+        assert np.array_equal(ga[k], gb[k]), k
+    assert np.array_equal(before["x"], after["x"]) and np.array_equal(before["y"], after["y"])
