@@ -82,34 +82,46 @@ def load_traffic():
     return d
 
 
-def measure_hbm(dev):
-    """Iteration rate and per-kernel GB/s on the large skewed LP (rows of
-    Zipf-distributed length), whose two matrices exceed the 256 MB Infinity
+HBM_WORKLOADS = {
+    "c3b": "c3b: m=2000000 n=5000000 nnz={nnz} Zipf(1.882) rows capped at 50,000, values +-10^U[-3,3]",
+    "c3a": "c3a: m=2000000 n=5000000 nnz={nnz} Zipf(1.5) rows capped at 50,000, values +-10^U[-3,3]",
+}
+
+
+def measure_hbm(dev, name="c3b", iters=640):
+    """Iteration rate and per-kernel GB/s on a large skewed LP (rows of
+    Zipf-distributed length) whose two matrices exceed the 256 MB Infinity
     Cache: the HBM-bound case."""
     import torch
 
     import lpgen
     from paper_2507_14051_amd import Problem
 
-    lp3 = lpgen.config("c3b", seed=1)
+    t0 = time.perf_counter()
+    lp3 = lpgen.config(name, seed=1, progress=lambda k, n: log(f"# {name}: rows chunk {k}/{n}") if k % 8 == 0 else None)
+    gen_s = time.perf_counter() - t0
     m3, n3, nnz3 = lp3.m, lp3.n, lp3.nnz
-    log(f"# hbm-bound c3b: m={m3} n={n3} nnz={nnz3} max_row={lp3.meta['max_row']}")
+    log(f"# hbm-bound {name}: m={m3} n={n3} nnz={nnz3} max_row={lp3.meta['max_row']} "
+        f"rows_at_cap={lp3.meta['rows_at_cap']} (generated in {gen_s:.0f} s)")
     t0 = time.perf_counter()
     p3 = Problem(lp3.A, lp3.c, lp3.lc, lp3.uc, lp3.lv, lp3.uv, device=dev)
     torch.cuda.synchronize()
     s3 = time.perf_counter() - t0
     del lp3
+    panels = p3.panels()
+    _, _, _, power_iters = p3.scaling()
+    log(f"# {name}: setup {s3:.2f} s (power iterations {power_iters}), panels {panels}")
     p3.solve(max_iter=64, tol=0.0, want_r=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    K3 = 640
-    p3.solve(max_iter=K3, tol=0.0, want_r=False)
+    p3.solve(max_iter=iters, tol=0.0, want_r=False)
     torch.cuda.synchronize()
-    it_s = K3 / (time.perf_counter() - t0)
-    pr3 = p3.profile(iters=100)
+    it_s = iters / (time.perf_counter() - t0)
+    pr3 = p3.profile(iters=min(100, iters))
     pb3, db3 = algorithmic_bytes(m3, n3, nnz3)
-    hbm = {"workload": f"c3b: m={m3} n={n3} nnz={nnz3} Zipf(1.882) rows capped at 50,000, "
-                       f"values +-10^U[-3,3]", "setup_s": round(s3, 3), "iters_per_s": round(it_s, 1),
+    hbm = {"workload": HBM_WORKLOADS[name].format(nnz=nnz3), "setup_s": round(s3, 3),
+           "power_iters": power_iters, "column_panels": panels[0], "long_rows": panels[1],
+           "iters_per_s": round(it_s, 1),
            "primal_us": round(pr3["primal_ms"] * 1e3, 2), "dual_us": round(pr3["dual_ms"] * 1e3, 2),
            "primal_gbs": round(pb3 / (pr3["primal_ms"] * 1e-3) / 1e9, 1),
            "dual_gbs": round(db3 / (pr3["dual_ms"] * 1e-3) / 1e9, 1),
@@ -131,8 +143,10 @@ def main():
     ap.add_argument("--profile-iters", type=int, default=400)
     ap.add_argument("--kernels-only", action="store_true",
                     help="only time the half-steps of --kernels-workload and a 256 MiB copy (for counter runs)")
-    ap.add_argument("--kernels-workload", default=WORKLOAD, choices=("c2", "c3b"))
+    ap.add_argument("--kernels-workload", default=WORKLOAD, choices=("c2", "c3b", "c3a"))
     ap.add_argument("--hbm-only", action="store_true", help="only the skewed-LP measurement (for profiling it)")
+    ap.add_argument("--hbm-workload", default="c3b", choices=("c3b", "c3a"),
+                    help="LP of --hbm-only (c3a: ~6.9e8 nonzeros, minutes to generate)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -145,7 +159,8 @@ def main():
 
     dev = torch.device("cuda:0")
     if args.hbm_only:
-        print(json.dumps({"hbm_only": True, "hbm_bound": measure_hbm(dev)}), flush=True)
+        iters = 640 if args.hbm_workload == "c3b" else 128
+        print(json.dumps({"hbm_only": True, "hbm_bound": measure_hbm(dev, args.hbm_workload, iters)}), flush=True)
         return
     wl = args.kernels_workload if args.kernels_only else WORKLOAD
     lp = lpgen.config(wl, seed=1)

@@ -97,28 +97,69 @@ def _columns_var(rng, n, lengths):
     return indptr, indices
 
 
-def gen(m, n, rowlen=8, eq_frac=0.3, free_frac=0.0, seed=1, values="normal",
-        zipf_alpha=None, cap=None, eq_rows=None) -> LP:
-    """The synthetic LP family described in the module docstring."""
-    rng = np.random.default_rng(seed)
-    if zipf_alpha is not None:
-        lengths = rng.zipf(zipf_alpha, size=m).astype(np.int64)
-        lengths = np.minimum(lengths, min(cap if cap is not None else n, n))
-        indptr, indices = _columns_var(rng, n, lengths)
-    else:
-        L = min(int(rowlen), n)
-        cols = _columns_fixed(rng, m, n, L)
-        indptr = np.arange(m + 1, dtype=np.int64) * L
-        indices = cols.ravel()
-    nnz = indices.size
+def _draw_values(rng, nnz, values):
     if values == "normal":
-        vals = rng.standard_normal(nnz)
-    elif values == "logu":
+        return rng.standard_normal(nnz)
+    if values == "logu":
         sign = np.where(rng.random(nnz) < 0.5, -1.0, 1.0)
-        vals = sign * 10.0 ** rng.uniform(-3.0, 3.0, size=nnz)
+        return sign * 10.0 ** rng.uniform(-3.0, 3.0, size=nnz)
+    raise ValueError(values)
+
+
+def _zipf_rows(rng, m, n, zipf_alpha, cap):
+    lengths = rng.zipf(zipf_alpha, size=m).astype(np.int64)
+    lengths = np.minimum(lengths, min(cap if cap is not None else n, n))
+    return _columns_var(rng, n, lengths)
+
+
+def _zipf_chunk(args):
+    """Rows of one chunk (its own seed): lengths, columns, values."""
+    seed_seq, m, n, zipf_alpha, cap, values = args
+    rng = np.random.default_rng(seed_seq)
+    indptr, indices = _zipf_rows(rng, m, n, zipf_alpha, cap)
+    return np.diff(indptr), indices.astype(np.int32), _draw_values(rng, indices.size, values)
+
+
+def _zipf_rows_chunked(seed, m, n, zipf_alpha, cap, values, chunks, progress=None):
+    """The Zipf-row matrix drawn in `chunks` row chunks, chunk k from the k-th
+    child of SeedSequence(seed) (so chunks are independent of each other);
+    progress(k, chunks) is called after each chunk."""
+    bounds = np.linspace(0, m, chunks + 1).astype(np.int64)
+    kids = np.random.SeedSequence(seed).spawn(chunks)
+    parts = []
+    for k in range(chunks):
+        parts.append(_zipf_chunk((kids[k], int(bounds[k + 1] - bounds[k]), n, zipf_alpha, cap, values)))
+        if progress:
+            progress(k + 1, chunks)
+    lengths = np.concatenate([p[0] for p in parts])
+    indptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(lengths, out=indptr[1:])
+    indices = np.concatenate([p[1] for p in parts])
+    del lengths
+    vals = np.concatenate([p[2] for p in parts])
+    return indptr, indices, vals
+
+
+def gen(m, n, rowlen=8, eq_frac=0.3, free_frac=0.0, seed=1, values="normal",
+        zipf_alpha=None, cap=None, eq_rows=None, row_chunks=0, progress=None) -> LP:
+    """The synthetic LP family described in the module docstring.  With
+    row_chunks > 0 (Zipf rows only) the matrix is drawn chunk by chunk from
+    child seeds; the rest of the recipe then continues from the generator of
+    `seed` itself."""
+    rng = np.random.default_rng(seed)
+    if zipf_alpha is not None and row_chunks > 0:
+        indptr, indices, vals = _zipf_rows_chunked(seed, m, n, zipf_alpha, cap, values, row_chunks, progress)
     else:
-        raise ValueError(values)
-    A = sp.csr_matrix((vals, indices.astype(np.int32), indptr), shape=(m, n))
+        if zipf_alpha is not None:
+            indptr, indices = _zipf_rows(rng, m, n, zipf_alpha, cap)
+        else:
+            L = min(int(rowlen), n)
+            cols = _columns_fixed(rng, m, n, L)
+            indptr = np.arange(m + 1, dtype=np.int64) * L
+            indices = cols.ravel()
+        vals = _draw_values(rng, indices.size, values)
+    nnz = indices.size
+    A = sp.csr_matrix((vals, indices.astype(np.int32, copy=False), indptr), shape=(m, n))
     xhat = rng.random(n)
     b = A @ xhat
     neq = int(eq_frac * m) if eq_rows is None else int(eq_rows)
@@ -198,16 +239,18 @@ CONFIGS = {
     "c1": dict(m=1000, n=2000, rowlen=5, eq_rows=500, free_frac=0.0, tol=1e-4),
     "c2": dict(m=100_000, n=200_000, rowlen=8, eq_frac=0.3, free_frac=0.2, tol=1e-8),
     "c3a": dict(m=2_000_000, n=5_000_000, zipf_alpha=1.5, cap=50_000, eq_frac=0.3,
-                free_frac=0.2, values="logu", tol=1e-8),
+                free_frac=0.2, values="logu", row_chunks=64, tol=1e-8),
     "c3b": dict(m=2_000_000, n=5_000_000, zipf_alpha=1.882, cap=50_000, eq_frac=0.3,
                 free_frac=0.2, values="logu", tol=1e-8),
     "c5": dict(m=50_000, n=100_000, rowlen=8, eq_frac=0.3, free_frac=0.2, tol=1e-8),
 }
 
 
-def config(name: str, seed: int = 1, scale: float = 1.0) -> LP:
+def config(name: str, seed: int = 1, scale: float = 1.0, progress=None) -> LP:
     """One of the named configurations; ``scale`` shrinks m and n together."""
     cfg = dict(CONFIGS[name])
+    if "row_chunks" in cfg:
+        cfg["progress"] = progress
     cfg.pop("tol")
     cfg["m"] = max(1, int(cfg["m"] * scale))
     cfg["n"] = max(1, int(cfg["n"] * scale))

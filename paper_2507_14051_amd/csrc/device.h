@@ -105,9 +105,10 @@ __device__ __forceinline__ T block_sum_to0(T v) {
 }
 
 // Each lane handles the nonzeros first + lane + k*STRIDE of [first, end) in
-// batches of kRbUnroll: all index and value loads of a batch are issued, then
-// all gathers, then the products, so a lane has a whole batch of gathers in
-// flight instead of one.
+// batches of U: all index and value loads of a batch are issued, then all
+// gathers, then the products, so a lane has a whole batch of gathers in
+// flight instead of one.  U (2, 4 or 8) follows the lane's share of the
+// range, so short ranges issue few masked loads and long ones deep batches.
 constexpr int kRbUnroll = 8;
 
 // NT: load the matrix arrays (idx, val) as streaming (non-temporal) data so a
@@ -119,27 +120,27 @@ __device__ __forceinline__ T ld(const T* p) {
 }
 
 // STAGE: write each product to lds[q - first] instead of summing.
-template <int STRIDE, bool STAGE, bool NT, typename ACC, typename V, typename X>
-__device__ __forceinline__ ACC strided_products(const int32_t* __restrict__ idx, const V* __restrict__ val,
-                                                const X* __restrict__ vec, int first, int end, int lane,
-                                                ACC* lds) {
+template <int STRIDE, int U, bool STAGE, bool NT, typename ACC, typename V, typename X>
+__device__ __forceinline__ ACC strided_batches(const int32_t* __restrict__ idx, const V* __restrict__ val,
+                                               const X* __restrict__ vec, int first, int end, int lane,
+                                               ACC* lds) {
   ACC part = 0;
-  for (int base = first + lane; base < end; base += STRIDE * kRbUnroll) {
+  for (int base = first + lane; base < end; base += STRIDE * U) {
     // Past the end, the clamped position repeats the last nonzero (a valid
     // address, so the loads need no branch) and its product is dropped.
-    int ix[kRbUnroll];
-    V vv[kRbUnroll];
+    int ix[U];
+    V vv[U];
 #pragma unroll
-    for (int u = 0; u < kRbUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int q = min(base + u * STRIDE, end - 1);
       ix[u] = ld<NT>(idx + q);
       vv[u] = ld<NT>(val + q);
     }
-    X g[kRbUnroll];
+    X g[U];
 #pragma unroll
-    for (int u = 0; u < kRbUnroll; ++u) g[u] = vec[ix[u]];
+    for (int u = 0; u < U; ++u) g[u] = vec[ix[u]];
 #pragma unroll
-    for (int u = 0; u < kRbUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int q = base + u * STRIDE;
       const ACC prod = q < end ? (ACC)vv[u] * (ACC)g[u] : ACC(0);
       if constexpr (STAGE) {
@@ -150,6 +151,19 @@ __device__ __forceinline__ ACC strided_products(const int32_t* __restrict__ idx,
     }
   }
   return part;
+}
+
+// The batch depth is uniform over the lanes that share [first, end) (a block
+// or a wave).  Either way a lane adds its products in increasing position, so
+// the result does not depend on the depth.
+template <int STRIDE, bool STAGE, bool NT, typename ACC, typename V, typename X>
+__device__ __forceinline__ ACC strided_products(const int32_t* __restrict__ idx, const V* __restrict__ val,
+                                                const X* __restrict__ vec, int first, int end, int lane,
+                                                ACC* lds) {
+  const int per_lane = (end - first + STRIDE - 1) / STRIDE;
+  if (per_lane <= 2) return strided_batches<STRIDE, 2, STAGE, NT, ACC>(idx, val, vec, first, end, lane, lds);
+  if (per_lane <= 4) return strided_batches<STRIDE, 4, STAGE, NT, ACC>(idx, val, vec, first, end, lane, lds);
+  return strided_batches<STRIDE, kRbUnroll, STAGE, NT, ACC>(idx, val, vec, first, end, lane, lds);
 }
 
 // Row sums of val .* vec[idx] over the calling block's nrows rows with
