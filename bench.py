@@ -139,7 +139,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--no-hbm", action="store_true", help="skip the HBM-bound skewed LP")
+    ap.add_argument("--no-hbm", action="store_true", help="skip the HBM-bound skewed LPs (c3b, c3a)")
     ap.add_argument("--profile-iters", type=int, default=400)
     ap.add_argument("--kernels-only", action="store_true",
                     help="only time the half-steps of --kernels-workload and a 256 MiB copy (for counter runs)")
@@ -239,19 +239,20 @@ def main():
         probm.close()
         log(f"# mixed: {mixed}")
 
-    hbm = None
+    hbm = hbm_a = None
     if not args.no_hbm:
-        hbm = measure_hbm(dev)
+        hbm = measure_hbm(dev, "c3b", 640)
+        hbm_a = measure_hbm(dev, "c3a", 128)
 
     cpu = None
     if not args.no_cpu:
         import oracle
-        K = 60
-        res = oracle.solve(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv,
-                           oracle.Params(tol=tol, max_iter=K, eta_override=eta))
+        K = 2000
+        res = oracle.solve(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, oracle.Params(tol=tol, max_iter=K))
         cpu = {"value": round(K / res.info["iter_s"], 3), "unit": "iter/s", "cores": 1, "kind": "oracle",
-               "sample": f"{K} oracle iterations of the same LP (eta given; scaling {res.info['setup_s']:.1f}s "
-                         f"excluded), NumPy/SciPy FP64 single thread; host nproc={os.cpu_count()}"}
+               "sample": f"{K} oracle iterations of the same LP (its own scaling and power iteration, "
+                         f"{res.info['setup_s']:.1f} s, not counted), NumPy/SciPy FP64 single thread; "
+                         f"host nproc={os.cpu_count()}"}
         log(f"# cpu: {cpu}")
 
     line = {
@@ -265,7 +266,7 @@ def main():
         "time_to_tol_s": round(elapsed / args.steps, 4), "iters_per_solve": infos[-1]["iters"],
         "restarts": infos[-1]["restarts"], "rel_kkt": infos[-1]["rel_kkt"], "all_optimal": ok,
         "setup_s": round(setup_wall, 4), "power_iters": power_iters,
-        "mixed": mixed, "hbm_bound": hbm, "roofline": roofline, "cpu_baseline": cpu,
+        "mixed": mixed, "hbm_bound": hbm, "hbm_bound_c3a": hbm_a, "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

@@ -11,7 +11,7 @@ import torch
 import lpgen
 from oracle.adjoint import unrolled_forward, unrolled_vjp
 from oracle.pdhg import Params
-from tests._gpu import announce, problem, rel
+from tests._gpu import announce, oracle_eta, problem, rel
 from tests.test_oracle_adjoint import kink_free_central_difference
 
 pytestmark = pytest.mark.gpu
@@ -42,8 +42,8 @@ def test_gradients_match_oracle(seed):
     lp = lpgen.config("c5", seed=seed, scale=0.01)      # m=500, n=1000, 8 nnz/row
     K, ckpt = 300, 40
     announce(f"adjoint vs oracle seed={seed} m={lp.m} n={lp.n} K={K} ckpt={ckpt}")
-    prob = problem(lp)
-    _, _, eta, _ = prob.scaling()
+    eta = oracle_eta(lp)
+    prob = problem(lp, eta=eta)
     rng = np.random.default_rng(seed)
     gx = rng.standard_normal(lp.n); gy = rng.standard_normal(lp.m)
     x, y, g = _grads(prob, lp, K, ckpt, gx, gy, eval_freq=16)
@@ -64,8 +64,8 @@ def test_gradients_long_rows_match_oracle():
     assert (np.diff(lp.A.indptr) > 4096).sum() > 10
     K, ckpt = 120, 25
     announce(f"adjoint long rows nnz={lp.nnz} K={K}")
-    prob = problem(lp)
-    _, _, eta, _ = prob.scaling()
+    eta = oracle_eta(lp)
+    prob = problem(lp, eta=eta)
     rng = np.random.default_rng(5)
     gx = rng.standard_normal(lp.n); gy = rng.standard_normal(lp.m)
     x, y, g = _grads(prob, lp, K, ckpt, gx, gy, eval_freq=16)

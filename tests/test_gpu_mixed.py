@@ -11,7 +11,7 @@ import lpgen
 import oracle
 from oracle.mixed import solve_mixed
 from oracle.pdhg import Params
-from tests._gpu import announce, np_out, problem, rel
+from tests._gpu import announce, np_out, oracle_eta, problem, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -20,8 +20,8 @@ def test_mixed_c1_matches_oracle_and_tolerance():
     from paper_2507_14051_amd import MIXED
     lp = lpgen.config("c1", seed=1)
     announce("mixed c1")
-    prob = problem(lp, precision=MIXED)
-    _, _, eta, _ = prob.scaling()
+    eta = oracle_eta(lp)
+    prob = problem(lp, eta=eta, precision=MIXED)
     T = 20
     out = prob.solve(tol=1e-8, trace_iters=T)
     tr = {k: v.cpu().numpy() for k, v in out["trace"].items()}

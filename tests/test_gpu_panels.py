@@ -16,7 +16,7 @@ import scipy.sparse as sp
 import lpgen
 import oracle
 from oracle.pdhg import Params
-from tests._gpu import announce, np_out, problem, rel
+from tests._gpu import announce, np_out, oracle_eta, problem, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -52,15 +52,15 @@ def _random_rows(rng, m, n, lengths):
     return sp.csr_matrix((rng.standard_normal(r.size), (r, c)), shape=(m, n))
 
 
-def _end_point_case(lp, K, panels, row_min, precision_mixed=False):
-    prob = problem(lp, column_panels=panels, panel_row_min=row_min)
+def _end_point_case(lp, K, panels, row_min):
+    eta = oracle_eta(lp)
+    prob = problem(lp, eta=eta, column_panels=panels, panel_row_min=row_min)
     P, nl = prob.panels()
     lens = np.diff(lp.A.indptr)
     assert P == 8 * ((panels + 7) // 8) and nl == int((lens > row_min).sum()) > 0
-    _, _, eta, _ = prob.scaling()
     out = np_out(prob.solve(tol=0.0, max_iter=K))
     prob.close()
-    plain = problem(lp, column_panels=0)
+    plain = problem(lp, eta=eta, column_panels=0)
     assert plain.panels() == (0, 0)
     ref_gpu = np_out(plain.solve(tol=0.0, max_iter=K))
     plain.close()
@@ -115,9 +115,9 @@ def test_panels_more_panels_than_columns():
 def test_panels_fp64_solve_to_tolerance_and_repeatable():
     lp = lpgen.config("c1", seed=3)
     announce("panels c1 solve 1e-8")
-    prob = problem(lp, column_panels=8, panel_row_min=3)
+    eta = oracle_eta(lp)
+    prob = problem(lp, eta=eta, column_panels=8, panel_row_min=3)
     assert prob.panels()[0] == 8
-    _, _, eta, _ = prob.scaling()
     a = np_out(prob.solve(tol=1e-8))
     b = np_out(prob.solve(tol=1e-8))
     c = np_out(prob.solve(tol=1e-8, graphs=0))

@@ -15,7 +15,7 @@ import scipy.sparse as sp
 import lpgen
 import oracle
 from oracle.pdhg import Params, power_norm, rescale
-from tests._gpu import announce, np_out, problem, rel
+from tests._gpu import announce, np_out, oracle_eta, problem, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -23,8 +23,8 @@ TRAJ_TOL = 1e-10
 
 
 def _trajectory_case(lp, T=100, **kw):
-    prob = problem(lp)
-    dr, dc, eta, pit = prob.scaling()
+    eta = oracle_eta(lp)
+    prob = problem(lp, eta=eta)
     out = prob.solve(trace_iters=T, **kw)
     ref = oracle.solve(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, Params(eta_override=eta, trace_iters=T, **kw))
     tr = {k: v.cpu().numpy() for k, v in out["trace"].items()}
@@ -126,8 +126,8 @@ def test_skewed_rows_match_oracle_over_restarts():
     PID weight keeps growing, so the comparison is at a fixed iteration count.)"""
     lp = lpgen.gen(2000, 5000, zipf_alpha=1.7, cap=1500, eq_frac=0.3, free_frac=0.2, values="logu", seed=2)
     announce("skewed 3000 iterations vs oracle")
-    prob = problem(lp)
-    _, _, eta, _ = prob.scaling()
+    eta = oracle_eta(lp)
+    prob = problem(lp, eta=eta)
     out = np_out(prob.solve(tol=1e-12, max_iter=3000))
     ref = oracle.solve(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, Params(tol=1e-12, max_iter=3000, eta_override=eta))
     assert out["info"]["status"] == ref.status == oracle.pdhg.ITER_LIMIT
