@@ -151,6 +151,7 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
   L->partial_blocks = N + 2;
   L->partials = c.take<double>(4 * L->partial_blocks * 8);
   L->results = c.take<double>(NSLOT * NQ);
+  L->fin_scratch = c.take<double>(4 * 256 * 8);
   L->pstate = c.take<PowerState>(1);
   L->flags = c.take<int32_t>(4);
   // transpose scratch

@@ -127,6 +127,7 @@ struct hlp_lp {
   double* partials = nullptr;
   int64_t partial_blocks = 0;  // capacity in blocks (each NQ doubles)
   double* results = nullptr;   // NSLOT * NQ
+  double* fin_scratch = nullptr;  // first-pass chunk results of large finalizes: 4 x 256 x 8
   hlp::PowerState* pstate = nullptr;
   int32_t* flags = nullptr;
   // setup scratch (transpose)

@@ -14,6 +14,8 @@
 // per-block partials summed in block order: results are bit-reproducible.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include <cmath>
 
 #include "device.h"
@@ -27,6 +29,8 @@ inline int nblocks(int64_t threads) { return (int)((threads + kBlock - 1) / kBlo
 
 // partial regions inside lp->partials, each `cap` blocks x 8 doubles
 constexpr int kRegionStride = 8;
+constexpr int64_t kFinDirect = 4096;  // regions up to this many blocks: one finalize pass
+constexpr int kFinChunks = 256;       // chunks of the first pass otherwise (hlp_lp::fin_scratch)
 inline double* region(hlp_lp* lp, int r) { return lp->partials + (int64_t)r * lp->partial_blocks * kRegionStride; }
 enum { R_PRIMAL = 0, R_DUAL = 1, R_KKT = 2, R_ROWS = 3 };
 
@@ -606,6 +610,30 @@ __global__ void k_finalize(FinArgs a) {
   }
 }
 
+// Large regions first go through this: block (c, r) reduces blocks
+// [c*chunk, (c+1)*chunk) of region r, all its quantities in one pass over
+// whole rows of partials, into out[(r*G + c)*kRegionStride + k]; k_finalize
+// then reduces the G chunk results in order.
+__global__ void k_finalize_chunks(FinArgs a, int64_t chunk, int32_t G, double* out) {
+  const Region R = a.r[blockIdx.y];
+  const int64_t b0 = (int64_t)blockIdx.x * chunk;
+  const int64_t b1 = min(R.nb, b0 + chunk);
+  double acc[kRegionStride];
+#pragma unroll
+  for (int k = 0; k < kRegionStride; ++k) acc[k] = 0.0;
+  for (int64_t b = b0 + threadIdx.x; b < b1; b += kBlock) {
+    const double2* row = reinterpret_cast<const double2*>(R.p + b * kRegionStride);
+#pragma unroll
+    for (int h = 0; h < kRegionStride / 2; ++h) {
+      const double2 v = row[h];
+      const bool m0 = (R.max_mask >> (2 * h)) & 1u, m1 = (R.max_mask >> (2 * h + 1)) & 1u;
+      acc[2 * h] = m0 ? (v.x > acc[2 * h] ? v.x : acc[2 * h]) : acc[2 * h] + v.x;
+      acc[2 * h + 1] = m1 ? (v.y > acc[2 * h + 1] ? v.y : acc[2 * h + 1]) : acc[2 * h + 1] + v.y;
+    }
+  }
+  block_reduce_store<kRegionStride>(acc, out + ((int64_t)blockIdx.y * G + blockIdx.x) * kRegionStride, R.max_mask);
+}
+
 // ============================================================================ dispatch helpers
 Region make_region(const double* p, int64_t nb, std::initializer_list<int> qs, uint32_t max_mask) {
   Region r{};
@@ -729,6 +757,17 @@ hipError_t launch_finalize(hlp_lp* lp, int32_t which, int32_t slot) {
   }
   if (which & 8) a.r[nr++] = make_region(region(lp, R_ROWS), nbd, {Q_RP2, Q_DOBJ_R, Q_VP}, 4u);
   if (nr == 0) return hipSuccess;
+  int64_t nbmax = 0;
+  for (int r = 0; r < nr; ++r) nbmax = std::max(nbmax, a.r[r].nb);
+  if (nbmax > kFinDirect) {
+    const int64_t chunk = std::max<int64_t>(kFinDirect, (nbmax + kFinChunks - 1) / kFinChunks);
+    const int32_t G = (int32_t)((nbmax + chunk - 1) / chunk);
+    hipLaunchKernelGGL(k_finalize_chunks, dim3(G, nr), dim3(kBlock), 0, lp->stream, a, chunk, G, lp->fin_scratch);
+    for (int r = 0; r < nr; ++r) {
+      a.r[r].p = lp->fin_scratch + (int64_t)r * G * kRegionStride;
+      a.r[r].nb = std::min<int64_t>(G, (a.r[r].nb + chunk - 1) / chunk);
+    }
+  }
   hipLaunchKernelGGL(k_finalize, dim3(nr), dim3(kBlock), 0, lp->stream, a);
   return hipGetLastError();
 }
