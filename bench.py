@@ -109,8 +109,9 @@ def measure_hbm(dev, name="c3b", iters=640):
     s3 = time.perf_counter() - t0
     del lp3
     panels = p3.panels()
+    dense = p3.dense()
     _, _, _, power_iters = p3.scaling()
-    log(f"# {name}: setup {s3:.2f} s (power iterations {power_iters}), panels {panels}")
+    log(f"# {name}: setup {s3:.2f} s (power iterations {power_iters}), panels {panels}, dense {dense}")
     p3.solve(max_iter=64, tol=0.0, want_r=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -121,6 +122,7 @@ def measure_hbm(dev, name="c3b", iters=640):
     pb3, db3 = algorithmic_bytes(m3, n3, nnz3)
     hbm = {"workload": HBM_WORKLOADS[name].format(nnz=nnz3), "setup_s": round(s3, 3),
            "power_iters": power_iters, "column_panels": panels[0], "long_rows": panels[1],
+           "narrow_panels": dense[0], "dense_rows": dense[1],
            "iters_per_s": round(it_s, 1),
            "primal_us": round(pr3["primal_ms"] * 1e3, 2), "dual_us": round(pr3["dual_ms"] * 1e3, 2),
            "primal_gbs": round(pb3 / (pr3["primal_ms"] * 1e-3) / 1e9, 1),

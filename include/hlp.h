@@ -113,6 +113,12 @@ typedef struct {
                               order in which the row sums are added; -1 */
   int32_t panel_row_min;   /* [setup] rows with more nonzeros than this are "long"
                               (>= 1); 16 */
+  int32_t dense_row_min;   /* [setup] with column panels on, long rows with at least
+                              this many nonzeros are "dense": their nonzeros are also
+                              grouped by narrow panels of 2048 columns, whose slice of
+                              xbar a block stages in LDS; the per-panel partial row sums
+                              are added in panel order.  0: no dense rows; otherwise
+                              > panel_row_min; 4096 */
 } hlp_params;
 
 /* Outcome of a solve.  Objectives and relative errors refer to the original
@@ -211,10 +217,12 @@ hlp_err hlp_lp_scaling(const hlp_lp* lp, double* d_r, double* d_c, double* eta, 
  * transpose).  Any pointer may be NULL. */
 hlp_err hlp_lp_transpose(const hlp_lp* lp, int32_t* col_ptr, int32_t* row_idx, double* val);
 
-/* The column-panel layout chosen at setup (hlp_params::column_panels): the
- * panel count (0: not used) and the number of long rows, through host
- * pointers (either may be NULL).  Errors: HLP_EINVAL for a NULL handle. */
-hlp_err hlp_lp_panels(const hlp_lp* lp, int32_t* panels, int32_t* long_rows);
+/* The column-panel layout chosen at setup (hlp_params::column_panels,
+ * dense_row_min): the panel count (0: not used), the number of long rows in
+ * those panels, the number of narrow panels and of dense rows, through host
+ * pointers (any may be NULL).  Errors: HLP_EINVAL for a NULL handle. */
+hlp_err hlp_lp_panels(const hlp_lp* lp, int32_t* panels, int32_t* long_rows, int32_t* dense_panels,
+                      int32_t* dense_rows);
 
 /*
  * Unrolled iterations with a tape for the reverse mode (an extension: the

@@ -22,7 +22,7 @@ __all__ = ["Problem", "solve", "HlpError", "FP64", "MIXED", "OPTIMAL", "ITER_LIM
            "NUMERICAL", "STATUS_NAMES", "hlp_params_default"]
 
 SETUP_FIELDS = ("precision", "eta_override", "ruiz_iters", "pock_chambolle", "power_max_iter", "power_tol",
-                "stream_matrix", "column_panels", "panel_row_min")
+                "stream_matrix", "column_panels", "panel_row_min", "dense_row_min")
 
 
 def _dev_tensor(a, dtype, device):
@@ -127,7 +127,11 @@ class Problem:
 
     def panels(self):
         """(panel count, long rows) of the column-panel layout; (0, 0) if unused."""
-        return hlp_lp_panels(self.handle)
+        return hlp_lp_panels(self.handle)[:2]
+
+    def dense(self):
+        """(narrow panel count, dense rows) of the LDS-staged layout; (0, 0) if unused."""
+        return hlp_lp_panels(self.handle)[2:]
 
     def profile(self, iters=200, **params):
         return hlp_profile_iterations(self.handle, self.params_for(**params), iters)

@@ -72,7 +72,7 @@ int32_t panel_count(int32_t n, const hlp_params* p) {
 }
 
 size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t precision, int32_t panels,
-             int32_t panel_row_min) {
+             int32_t panel_row_min, int32_t dense_row_min) {
   Carver c{static_cast<char*>(base)};
   const bool mixed = precision == HLP_MIXED;
   const int64_t N = std::max<int64_t>(m, n);
@@ -88,7 +88,18 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
   if (nLmax == 0) panels = 0;
   L->panels = panels;  // reserved count; hlp_lp_create may switch the layout off
   L->nL_cap = (int32_t)nLmax;
-  const int64_t RB = std::max<int64_t>(N, R);
+  // dense rows (at least dense_row_min nonzeros): narrow panels of kDenseW columns
+  int64_t nDmax = 0, RD = 0, PD = 0, GD = 0;
+  if (panels > 0 && dense_row_min > panel_row_min) {
+    PD = ((int64_t)n + kDenseW - 1) / kDenseW;
+    GD = (PD + kDenseGroup - 1) / kDenseGroup;
+    nDmax = std::min<int64_t>(m, nnz / dense_row_min);
+    RD = PD * nDmax;
+    if (RD + PD + 2 >= (int64_t(1) << 30)) nDmax = RD = 0;
+  }
+  L->nD_cap = (int32_t)nDmax;
+  L->dense_P = (int32_t)PD;
+  const int64_t RB = std::max<int64_t>(N, std::max(R, RD));
   L->rp = c.take<int32_t>((int64_t)m + 1);
   L->col = c.take<int32_t>(nnz);
   L->val0 = c.take<double>(nnz);
@@ -153,7 +164,7 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
   L->results = c.take<double>(NSLOT * NQ);
   L->fin_scratch = c.take<double>(4 * 256 * 8);
   L->pstate = c.take<PowerState>(1);
-  L->flags = c.take<int32_t>(4);
+  L->flags = c.take<int32_t>(8);
   // transpose scratch
   L->kA = c.take<int32_t>(nnz);
   L->kB = c.take<int32_t>(std::max<int64_t>(nnz, (int64_t)n + 1));
@@ -184,8 +195,21 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
     L->rbxP = c.take<int32_t>(4 * (R + 1));
     L->tabP = c.take<int32_t>(4 * (R + 1));
     L->rowc = c.take<int32_t>(nnz);
-    L->pscrA = c.take<int32_t>(std::max<int64_t>(m, R) + 1);
-    L->pscrB = c.take<int32_t>(std::max<int64_t>(m, R) + 1);
+    L->pscrA = c.take<int32_t>(RB + 1);
+    L->pscrB = c.take<int32_t>(RB + 1);
+    L->pscrC = c.take<int32_t>((int64_t)m + 1);
+    L->dlid = c.take<int32_t>((int64_t)m + 1);
+  }
+  if (nDmax > 0) {
+    L->ppD = c.take<int32_t>(RD + 1);
+    L->pcolD = c.take<int32_t>(nnz);
+    L->pvalD = c.take<double>(nnz);
+    L->pval32D = mixed ? c.take<float>(nnz) : nullptr;
+    L->partD = c.take<double>(RD);
+    L->part2D = c.take<double>(GD * nDmax);
+    L->rbD = c.take<int32_t>(RD + 2);
+    L->rbxD = c.take<int32_t>(4 * (RD + 1));
+    L->tilesD = c.take<int32_t>(4 * (RD + PD + 1));
   }
   // power iteration vectors alias iteration buffers (setup only)
   L->pv = L->rbuf;
@@ -234,6 +258,7 @@ hlp_err hlp_params_default(hlp_params* p) {
   p->stream_matrix = -1;
   p->column_panels = -1;
   p->panel_row_min = 16;
+  p->dense_row_min = 4096;
   return HLP_OK;
 }
 
@@ -258,7 +283,8 @@ hlp_err hlp_workspace_bytes(int32_t m, int32_t n, int64_t nnz, const hlp_params*
   hlp_params d;
   hlp_params_default(&d);
   if (!p) p = &d;
-  *bytes = carve(nullptr, nullptr, m, n, nnz, p->precision, panel_count(n, p), p->panel_row_min);
+  *bytes = carve(nullptr, nullptr, m, n, nnz, p->precision, panel_count(n, p), p->panel_row_min,
+                 p->dense_row_min);
   return HLP_OK;
 }
 
@@ -268,56 +294,96 @@ static hlp_err read_flags(hlp_lp* lp, int* out) {
   return HLP_OK;
 }
 
-// Column-panel layout of the long rows (see hlp_params::column_panels); P is
-// the reserved panel count.  Leaves lp->panels = 0 when the layout is not used.
-static hlp_err build_panels(hlp_lp* lp, int32_t P, int32_t T, bool automatic) {
-  lp->panels = 0;
-  if (P <= 0 || lp->m == 0 || lp->n == 0 || lp->nnz == 0) return HLP_OK;
-  HLP_HIP(launch_panel_split(lp, T, lp->flags));
-  int32_t cnt[4] = {0, 0, 0, 0};
-  HLP_HIP(hipMemcpyAsync(cnt, lp->flags, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, lp->stream));
+// First row block of each panel (panels start blocks), read back to the host.
+static hlp_err panel_starts(hlp_lp* lp, const int32_t* rbx, int32_t nb, int32_t rows_per_panel, int32_t P,
+                            std::vector<int32_t>& pstart) {
+  pstart.assign((size_t)P + 1, -1);
+  HLP_HIP(launch_panel_starts(rbx, nb, rows_per_panel, lp->pscrA, lp->stream));
+  HLP_HIP(hipMemcpyAsync(pstart.data(), lp->pscrA, (size_t)P * sizeof(int32_t), hipMemcpyDeviceToHost, lp->stream));
   HLP_HIP(hipStreamSynchronize(lp->stream));
-  const int32_t nL = cnt[0];
-  const int64_t nnz_long = lp->nnz - cnt[1];
-  if (nL < 1 || nL > lp->nL_cap) return HLP_OK;
-  if (automatic && 2 * nnz_long < lp->nnz) return HLP_OK;
+  pstart[P] = nb;
+  for (int32_t q = 0; q < P; ++q)
+    if (pstart[q] < 0 || pstart[q + 1] <= pstart[q]) {
+      set_error("column panels: inconsistent block table");
+      return HLP_EUNSUPPORTED;
+    }
+  return HLP_OK;
+}
+
+// Column-panel layout of the long and dense rows (see hlp_params::column_panels
+// and dense_row_min); P is the reserved panel count.  Leaves lp->panels = 0
+// when the layout is not used.
+static hlp_err build_panels(hlp_lp* lp, int32_t P, int32_t T, int32_t Ld, bool automatic) {
+  lp->panels = 0;
+  lp->nL = lp->nD = 0;
+  if (P <= 0 || lp->m == 0 || lp->n == 0 || lp->nnz == 0) return HLP_OK;
+  if (lp->nD_cap == 0) Ld = 0;  // no room reserved for dense rows
+  HLP_HIP(launch_panel_split(lp, T, Ld, lp->flags));
+  int32_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  HLP_HIP(hipMemcpyAsync(cnt, lp->flags, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, lp->stream));
+  HLP_HIP(hipStreamSynchronize(lp->stream));
+  const int32_t nL = cnt[0], nD = cnt[2];
+  const int64_t nnz_split = lp->nnz - cnt[1];
+  if (nL + nD < 1 || nL + nD > lp->nL_cap || nD > lp->nD_cap) return HLP_OK;
+  if (automatic && 2 * nnz_split < lp->nnz) return HLP_OK;
   lp->panels = P;
   lp->nL = nL;
+  lp->nD = nD;
   lp->panel_w = (int32_t)(((int64_t)lp->n + P - 1) / P);
+  lp->dense_w = kDenseW;
   HLP_HIP(launch_panel_layout(lp, lp->flags));
-  HLP_HIP(hipMemcpyAsync(cnt, lp->flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, lp->stream));
+  HLP_HIP(hipMemcpyAsync(cnt, lp->flags, 6 * sizeof(int32_t), hipMemcpyDeviceToHost, lp->stream));
   HLP_HIP(hipStreamSynchronize(lp->stream));
-  lp->nbS = cnt[2];
-  lp->nbP = cnt[3];
+  lp->nbS = cnt[3];
+  lp->nbP = nL > 0 ? cnt[4] : 0;
+  lp->nbD = nD > 0 ? cnt[5] : 0;
   HLP_HIP(launch_panel_remap(lp));
-  // blocks of panel p: [pstart[p], pstart[p+1]); dealt to XCD p mod 8 in panel order
-  std::vector<int32_t> pstart(P + 1);
-  HLP_HIP(launch_panel_starts(lp, lp->pscrA));
-  HLP_HIP(hipMemcpyAsync(pstart.data(), lp->pscrA, P * sizeof(int32_t), hipMemcpyDeviceToHost, lp->stream));
-  HLP_HIP(hipStreamSynchronize(lp->stream));
-  pstart[P] = lp->nbP;
-  int32_t off = 0, widest = 0;
-  for (int x = 0; x < 8; ++x) {
-    lp->poff[x] = off;
-    for (int q = x; q < P; q += 8) {
-      const int32_t len = pstart[q + 1] - pstart[q];
-      if (len < 1 || off + len > lp->nbP) {
-        set_error("column panels: inconsistent block table");
-        return HLP_EUNSUPPORTED;
+  std::vector<int32_t> pstart;
+  lp->nbPgrid = 0;
+  for (int k = 0; k < 9; ++k) lp->poff[k] = 0;
+  if (nL > 0) {
+    // blocks of panel q: [pstart[q], pstart[q+1]); dealt to XCD q mod 8 in panel order
+    HLP_TRY(panel_starts(lp, lp->rbxP, lp->nbP, nL, P, pstart));
+    int32_t off = 0, widest = 0;
+    for (int x = 0; x < 8; ++x) {
+      lp->poff[x] = off;
+      for (int q = x; q < P; q += 8) {
+        const int32_t len = pstart[q + 1] - pstart[q];
+        HLP_HIP(hipMemcpyAsync(lp->tabP + 4 * (int64_t)off, lp->rbxP + 4 * (int64_t)pstart[q],
+                               16 * (size_t)len, hipMemcpyDeviceToDevice, lp->stream));
+        off += len;
       }
-      HLP_HIP(hipMemcpyAsync(lp->tabP + 4 * (int64_t)off, lp->rbxP + 4 * (int64_t)pstart[q],
-                             16 * (size_t)len, hipMemcpyDeviceToDevice, lp->stream));
-      off += len;
+      widest = std::max(widest, off - lp->poff[x]);
     }
-    widest = std::max(widest, off - lp->poff[x]);
+    lp->poff[8] = off;
+    if (off != lp->nbP) {
+      set_error("column panels: inconsistent block table");
+      return HLP_EUNSUPPORTED;
+    }
+    lp->nbPgrid = 8 * widest;
   }
-  lp->poff[8] = off;
-  if (off != lp->nbP) {
-    set_error("column panels: inconsistent block table");
-    return HLP_EUNSUPPORTED;
-  }
-  lp->nbPgrid = 8 * widest;
   lp->nbC = (nL + 255) / 256;
+  lp->ntilesD = 0;
+  lp->nbCD = (nD + 255) / 256;
+  if (nD > 0) {
+    // tiles: up to kTileBlocks consecutive row blocks of one narrow panel
+    HLP_TRY(panel_starts(lp, lp->rbxD, lp->nbD, nD, lp->dense_P, pstart));
+    std::vector<int32_t> tiles;
+    for (int32_t q = 0; q < lp->dense_P; ++q)
+      for (int32_t b = pstart[q]; b < pstart[q + 1]; b += kTileBlocks) {
+        tiles.push_back(b);
+        tiles.push_back(std::min(pstart[q + 1], b + kTileBlocks));
+        tiles.push_back(q);
+        tiles.push_back(0);
+      }
+    lp->ntilesD = (int32_t)(tiles.size() / 4);
+    if ((int64_t)lp->ntilesD > (int64_t)lp->dense_P * lp->nD_cap + lp->dense_P + 1) {
+      set_error("dense panels: tile table overflow");
+      return HLP_EUNSUPPORTED;
+    }
+    HLP_HIP(hipMemcpyAsync(lp->tilesD, tiles.data(), tiles.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                           lp->stream));
+  }
   HLP_HIP(hipStreamSynchronize(lp->stream));
   return HLP_OK;
 }
@@ -375,12 +441,13 @@ hlp_err hlp_lp_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr,
     set_error("bad setup parameters (ruiz_iters >= 0, power_max_iter >= 1, power_tol >= 0, finite eta_override >= 0)");
     return HLP_EINVAL;
   }
-  if (p->column_panels < -1 || p->panel_row_min < 1) {
-    set_error("bad setup parameters (column_panels >= -1, panel_row_min >= 1)");
+  if (p->column_panels < -1 || p->panel_row_min < 1 ||
+      (p->dense_row_min != 0 && p->dense_row_min <= p->panel_row_min)) {
+    set_error("bad setup parameters (column_panels >= -1, panel_row_min >= 1, dense_row_min 0 or > panel_row_min)");
     return HLP_EINVAL;
   }
   const int32_t P = panel_count(n, p);
-  size_t need = carve(nullptr, nullptr, m, n, nnz, p->precision, P, p->panel_row_min);
+  size_t need = carve(nullptr, nullptr, m, n, nnz, p->precision, P, p->panel_row_min, p->dense_row_min);
   if (workspace_bytes < need) {
     set_error("workspace too small: need " + std::to_string(need) + " bytes");
     return HLP_ENOMEM;
@@ -396,7 +463,7 @@ hlp_err hlp_lp_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr,
   lp->nnz = nnz;
   lp->stream = reinterpret_cast<hipStream_t>(hip_stream);
   lp->precision = p->precision;
-  carve(lp, workspace, m, n, nnz, p->precision, P, p->panel_row_min);
+  carve(lp, workspace, m, n, nnz, p->precision, P, p->panel_row_min, p->dense_row_min);
   auto fail = [&](hlp_err e) {
     delete lp;
     return e;
@@ -443,7 +510,8 @@ hlp_err hlp_lp_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr,
   // 3. rescaling of A, then the vectors
   if (hipError_t e = launch_rescale(lp, p->ruiz_iters, p->pock_chambolle); e != hipSuccess)
     return fail(hip_fail(e, "rescale"));
-  if (hlp_err e = build_panels(lp, P, p->panel_row_min, p->column_panels == -1); e != HLP_OK) return fail(e);
+  if (hlp_err e = build_panels(lp, P, p->panel_row_min, p->dense_row_min, p->column_panels == -1); e != HLP_OK)
+    return fail(e);
   if (hlp_err e = validate_and_scale_vectors(lp, c, lc, uc, lv, uv); e != HLP_OK) return fail(e);
   // 4. stepsize
   if (p->eta_override > 0.0) {
@@ -511,13 +579,17 @@ hlp_err hlp_lp_transpose(const hlp_lp* lp, int32_t* col_ptr, int32_t* row_idx, d
   return HLP_OK;
 }
 
-hlp_err hlp_lp_panels(const hlp_lp* lp, int32_t* panels, int32_t* long_rows) {
+hlp_err hlp_lp_panels(const hlp_lp* lp, int32_t* panels, int32_t* long_rows, int32_t* dense_panels,
+                      int32_t* dense_rows) {
   if (!lp) {
     set_error("NULL handle");
     return HLP_EINVAL;
   }
+  const bool on = lp->panels > 0;
   if (panels) *panels = lp->panels;
-  if (long_rows) *long_rows = lp->panels ? lp->nL : 0;
+  if (long_rows) *long_rows = on ? lp->nL : 0;
+  if (dense_panels) *dense_panels = on && lp->nD > 0 ? lp->dense_P : 0;
+  if (dense_rows) *dense_rows = on ? lp->nD : 0;
   return HLP_OK;
 }
 

@@ -122,8 +122,8 @@ __device__ __forceinline__ T ld(const T* p) {
 // STAGE: write each product to lds[q - first] instead of summing.
 template <int STRIDE, int U, bool STAGE, bool NT, typename ACC, typename V, typename X>
 __device__ __forceinline__ ACC strided_batches(const int32_t* __restrict__ idx, const V* __restrict__ val,
-                                               const X* __restrict__ vec, int first, int end, int lane,
-                                               ACC* lds) {
+                                               const X* __restrict__ vec, int xoff, int first, int end,
+                                               int lane, ACC* lds) {
   ACC part = 0;
   for (int base = first + lane; base < end; base += STRIDE * U) {
     // Past the end, the clamped position repeats the last nonzero (a valid
@@ -138,7 +138,7 @@ __device__ __forceinline__ ACC strided_batches(const int32_t* __restrict__ idx, 
     }
     X g[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) g[u] = vec[ix[u]];
+    for (int u = 0; u < U; ++u) g[u] = vec[ix[u] - xoff];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int q = base + u * STRIDE;
@@ -158,25 +158,28 @@ __device__ __forceinline__ ACC strided_batches(const int32_t* __restrict__ idx, 
 // the result does not depend on the depth.
 template <int STRIDE, bool STAGE, bool NT, typename ACC, typename V, typename X>
 __device__ __forceinline__ ACC strided_products(const int32_t* __restrict__ idx, const V* __restrict__ val,
-                                                const X* __restrict__ vec, int first, int end, int lane,
-                                                ACC* lds) {
+                                                const X* __restrict__ vec, int xoff, int first, int end,
+                                                int lane, ACC* lds) {
   const int per_lane = (end - first + STRIDE - 1) / STRIDE;
-  if (per_lane <= 2) return strided_batches<STRIDE, 2, STAGE, NT, ACC>(idx, val, vec, first, end, lane, lds);
-  if (per_lane <= 4) return strided_batches<STRIDE, 4, STAGE, NT, ACC>(idx, val, vec, first, end, lane, lds);
-  return strided_batches<STRIDE, kRbUnroll, STAGE, NT, ACC>(idx, val, vec, first, end, lane, lds);
+  if (per_lane <= 2)
+    return strided_batches<STRIDE, 2, STAGE, NT, ACC>(idx, val, vec, xoff, first, end, lane, lds);
+  if (per_lane <= 4)
+    return strided_batches<STRIDE, 4, STAGE, NT, ACC>(idx, val, vec, xoff, first, end, lane, lds);
+  return strided_batches<STRIDE, kRbUnroll, STAGE, NT, ACC>(idx, val, vec, xoff, first, end, lane, lds);
 }
 
-// Row sums of val .* vec[idx] over the calling block's nrows rows with
+// Row sums of val .* vec[idx - xoff] over the calling block's nrows rows with
 // nonzeros [ps, pe); thread t (own: t < nrows) holds the pointers [a0, a1) of
 // its row and gets that row's sum (in a single-row block every thread gets
-// it).  Deterministic in every kind of block.
+// it).  Deterministic in every kind of block.  (xoff: vec holds the slice of
+// the vector that starts at index xoff, e.g. a slice staged in LDS.)
 template <typename ACC, bool NT = false, typename V, typename X>
 __device__ __forceinline__ ACC rb_dot(const int32_t* __restrict__ idx, const V* __restrict__ val,
                                       const X* __restrict__ vec, int ps, int pe, int a0, int a1,
-                                      bool own, int nrows, ACC* lds) {
+                                      bool own, int nrows, ACC* lds, int xoff = 0) {
   const int tid = threadIdx.x;
   if (nrows == 1)
-    return block_sum_to0(strided_products<kBlock, false, NT, ACC>(idx, val, vec, ps, pe, tid, lds));
+    return block_sum_to0(strided_products<kBlock, false, NT, ACC>(idx, val, vec, xoff, ps, pe, tid, lds));
   if (pe - ps > nrows * kRbSerial) {  // medium rows (a block of short rows has at most kRbSerial per row)
     __shared__ int sh_ptr[kWaves + 1];
     __shared__ ACC sh_sum[kWaves];
@@ -187,14 +190,15 @@ __device__ __forceinline__ ACC rb_dot(const int32_t* __restrict__ idx, const V* 
     __syncthreads();
     const int w = tid >> 6;
     if (w < nrows) {
-      const ACC part = strided_products<64, false, NT, ACC>(idx, val, vec, sh_ptr[w], sh_ptr[w + 1], tid & 63, lds);
+      const ACC part =
+          strided_products<64, false, NT, ACC>(idx, val, vec, xoff, sh_ptr[w], sh_ptr[w + 1], tid & 63, lds);
       const ACC sum = wave_sum(part);
       if ((tid & 63) == 0) sh_sum[w] = sum;
     }
     __syncthreads();
     return own ? sh_sum[tid] : ACC(0);
   }
-  strided_products<kBlock, true, NT, ACC>(idx, val, vec, ps, pe, tid, lds);
+  strided_products<kBlock, true, NT, ACC>(idx, val, vec, xoff, ps, pe, tid, lds);
   __syncthreads();
   ACC acc = 0;
   if (own)

@@ -99,7 +99,20 @@ struct hlp_lp {
   // their y entries (index m + l); gathered by the plain primal half-steps
   int32_t* rowc = nullptr;
   int32_t *rbS = nullptr, *rbxS = nullptr, *rbP = nullptr, *rbxP = nullptr, *tabP = nullptr;
-  int32_t *pscrA = nullptr, *pscrB = nullptr;  // setup scratch
+  int32_t *pscrA = nullptr, *pscrB = nullptr, *pscrC = nullptr;  // setup scratch
+  // Dense rows (at least dense_min nonzeros; a subset of the rows taken out of
+  // AS, listed after the long rows in lrow): AD = their nonzeros grouped by
+  // narrow panels of dense_w columns, row q*nD + d = the part of dense row
+  // lrow[nL + d] in narrow panel q.  A tile = consecutive row blocks of one
+  // narrow panel, reduced by one block with the panel's slice of xbar in LDS.
+  int32_t dense_min = 0, dense_P = 0, dense_w = 0, nD = 0, nD_cap = 0;
+  int32_t *dlid = nullptr, *ppD = nullptr, *pcolD = nullptr;
+  double* pvalD = nullptr;
+  float* pval32D = nullptr;
+  double* partD = nullptr;   // dense_P * nD partial sums (float in the FP32 path)
+  double* part2D = nullptr;  // group sums of 64 narrow panels: ceil(dense_P / 64) * nD
+  int32_t *rbD = nullptr, *rbxD = nullptr, *tilesD = nullptr;
+  int32_t nbD = 0, ntilesD = 0, nbCD = 0;
   int32_t nbS = 0, nbP = 0, nbPgrid = 0, nbC = 0;
   int32_t poff[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // blocks of XCD x: tabP[poff[x] .. poff[x+1])
   int64_t rbtmp_rows = 0;             // capacity of the row-block scratch (rows)
@@ -129,7 +142,7 @@ struct hlp_lp {
   double* results = nullptr;   // NSLOT * NQ
   double* fin_scratch = nullptr;  // first-pass chunk results of large finalizes: 4 x 256 x 8
   hlp::PowerState* pstate = nullptr;
-  int32_t* flags = nullptr;
+  int32_t* flags = nullptr;   // 8 ints: validation flags and setup counts
   // setup scratch (transpose)
   int32_t *kA = nullptr, *kB = nullptr, *vA = nullptr, *vB = nullptr, *rowof = nullptr;
   int32_t *hist = nullptr, *scan_tmp = nullptr;
@@ -159,7 +172,10 @@ hlp_err hip_fail(hipError_t e, const char* what);
 // ---------------------------------------------------------------- layout
 // Carve the workspace.  With lp->... == nullptr base, only computes the size.
 size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t precision, int32_t panels,
-             int32_t panel_row_min);
+             int32_t panel_row_min, int32_t dense_row_min);
+constexpr int32_t kDenseW = 2048;     // columns per narrow panel (its FP64 slice: 16 KB of LDS)
+constexpr int32_t kDenseGroup = 64;   // narrow panels summed per group
+constexpr int32_t kTileBlocks = 16;   // row blocks per tile
 // Panels reserved for these sizes and parameters (0: none).
 int32_t panel_count(int32_t n, const hlp_params* p);
 
@@ -198,9 +214,13 @@ hipError_t launch_build_row_blocks(hlp_lp* lp, const int32_t* ptr, int32_t rows,
                                    int32_t* count, int32_t period = 0);
 // Column panels: long-row split (returns nL and the short-part nonzero count
 // through counts[0..1] on the device), then the panel layout and its blocks.
-hipError_t launch_panel_split(hlp_lp* lp, int32_t T, int32_t* counts);
+// counts[0] = long rows, counts[1] = nonzeros of the short part, counts[2] = dense rows.
+hipError_t launch_panel_split(hlp_lp* lp, int32_t T, int32_t Ld, int32_t* counts);
+// AS, the long rows' layout (if nL > 0) and the dense rows' layout (if nD > 0);
+// block counts of AS, AP and AD go to counts[3], counts[4], counts[5].
 hipError_t launch_panel_layout(hlp_lp* lp, int32_t* counts);
-hipError_t launch_panel_starts(hlp_lp* lp, int32_t* pstart);
+hipError_t launch_panel_starts(const int32_t* rbx, int32_t nb, int32_t rows_per_panel, int32_t* pstart,
+                               hipStream_t s);
 hipError_t launch_panel_remap(hlp_lp* lp);
 hipError_t launch_set_step(hlp_lp* lp, double tau, double sigma, double gamma, int64_t k0, double P = 1.0,
                            double D = 1.0);

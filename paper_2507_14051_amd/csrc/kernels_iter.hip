@@ -207,6 +207,64 @@ __device__ __forceinline__ T panel_sum(const T* __restrict__ part, int32_t P, in
   return h;
 }
 
+// Dense rows: a tile is up to kTileBlocks row blocks of one narrow panel of
+// AD; the block stages the panel's slice of the vector in LDS once and
+// gathers from there.
+template <typename T>
+struct DenseDotArgs {
+  const int4* tiles; const int4* rbx; const int32_t* pp; const int32_t* pcol; const T* pval; const T* vec;
+  T* out; int32_t n;
+};
+
+template <typename T, bool NT>
+__global__ __launch_bounds__(kBlock) void k_dense_dot(DenseDotArgs<T> p) {
+  __shared__ T xs[kDenseW];
+  __shared__ T lds[kRbLds];
+  const int4 tile = p.tiles[blockIdx.x];
+  const int c0 = tile.z * kDenseW;
+  const int nc = min(kDenseW, p.n - c0);
+  for (int c = threadIdx.x; c < nc; c += kBlock) xs[c] = p.vec[c0 + c];
+  __syncthreads();
+  for (int b = tile.x; b < tile.y; ++b) {  // uniform over the block
+    const int4 blk = p.rbx[b];
+    const int r = blk.x + threadIdx.x;
+    const bool own = r < blk.y;
+    int a0 = 0, a1 = 0;
+    if (own) { a0 = p.pp[r]; a1 = p.pp[r + 1]; }
+    const T acc = rb_dot<T, NT>(p.pcol, p.pval, xs, blk.z, blk.w, a0, a1, own, blk.y - blk.x, lds, c0);
+    if (own) p.out[r] = acc;
+  }
+}
+
+// Group sums of kDenseGroup narrow panels, in panel order:
+// out[g*nD + d] = sum over q in group g of part[q*nD + d].
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dense_combine(const T* __restrict__ part, int32_t nD, int32_t P,
+                                                          T* __restrict__ out) {
+  const int d = blockIdx.x * kBlock + threadIdx.x;
+  const int g = blockIdx.y;
+  if (d >= nD) return;
+  const int q0 = g * kDenseGroup, q1 = min(P, q0 + kDenseGroup);
+  T h = T(0);
+  int q = q0;
+  for (; q + 8 <= q1; q += 8) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(q + u) * nD + d];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) h += v[u];
+  }
+  for (; q < q1; ++q) h += part[(int64_t)q * nD + d];
+  out[(int64_t)g * nD + d] = h;
+}
+
+template <typename T>
+__device__ __forceinline__ T group_sum(const T* __restrict__ part2, int32_t G, int32_t nD, int d) {
+  T h = T(0);
+  for (int g = 0; g < G; ++g) h += part2[(int64_t)g * nD + d];
+  return h;
+}
+
 __device__ __forceinline__ bool is_long(const uint32_t* __restrict__ bits, int i) {
   return (bits[i >> 5] >> (i & 31)) & 1u;
 }
@@ -217,8 +275,8 @@ static_assert(kBlock == 256, "k_dual_pn: one long row per thread of 256-thread b
 struct DualPanelArgs {
   const int4* rb; const int32_t* sp; const int32_t* scol; const double* sval; const double* xbar;
   double* y; const double* ya; const double* lc; const double* uc; const StepDev* step;
-  const uint32_t* lbits; const int32_t* lrow; const double* part;
-  int32_t P, nL, nbS, j, m;
+  const uint32_t* lbits; const int32_t* lrow; const double* part; const double* part2;
+  int32_t P, nL, nbS, j, m, nbC, nD, G;
 };
 
 template <bool NT>
@@ -238,13 +296,22 @@ __global__ __launch_bounds__(kBlock) void k_dual_pn(DualPanelArgs p) {
       if (own) { yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i]; }
     }
     h = rb_dot<double, NT>(p.scol, p.sval, p.xbar, blk.z, blk.w, a0, a1, in, blk.y - blk.x, lds);
-  } else {
+  } else if ((int)blockIdx.x < p.nbS + p.nbC) {
     l = ((int)blockIdx.x - p.nbS) * kBlock + threadIdx.x;
     own = l < p.nL;
     if (own) {
       i = p.lrow[l];
       yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i];
       h = panel_sum(p.part, p.P, p.nL, l);
+    }
+  } else {
+    const int d = ((int)blockIdx.x - p.nbS - p.nbC) * kBlock + threadIdx.x;
+    own = d < p.nD;
+    if (own) {
+      l = p.nL + d;
+      i = p.lrow[l];
+      yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i];
+      h = group_sum(p.part2, p.G, p.nD, d);
     }
   }
   if (own) {
@@ -260,8 +327,8 @@ __global__ __launch_bounds__(kBlock) void k_dual_pn(DualPanelArgs p) {
 struct Dual32PanelArgs {
   const int4* rb; const int32_t* sp; const int32_t* scol; const float* sval; const float* xbar;
   float* y; const float* ya; const float* lc; const float* uc; const float* b; const StepDev* step;
-  const uint32_t* lbits; const int32_t* lrow; const float* part;
-  int32_t P, nL, nbS, j, m;
+  const uint32_t* lbits; const int32_t* lrow; const float* part; const float* part2;
+  int32_t P, nL, nbS, j, m, nbC, nD, G;
 };
 
 template <bool NT>
@@ -281,13 +348,22 @@ __global__ __launch_bounds__(kBlock) void k_dual32_pn(Dual32PanelArgs p) {
       if (own) { yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i]; bi = p.b[i]; }
     }
     h = rb_dot<float, NT>(p.scol, p.sval, p.xbar, blk.z, blk.w, a0, a1, in, blk.y - blk.x, lds);
-  } else {
+  } else if ((int)blockIdx.x < p.nbS + p.nbC) {
     l = ((int)blockIdx.x - p.nbS) * kBlock + threadIdx.x;
     own = l < p.nL;
     if (own) {
       i = p.lrow[l];
       yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i]; bi = p.b[i];
       h = panel_sum(p.part, p.P, p.nL, l);
+    }
+  } else {
+    const int d = ((int)blockIdx.x - p.nbS - p.nbC) * kBlock + threadIdx.x;
+    own = d < p.nD;
+    if (own) {
+      l = p.nL + d;
+      i = p.lrow[l];
+      yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i]; bi = p.b[i];
+      h = group_sum(p.part2, p.G, p.nD, d);
     }
   }
   if (own) {
@@ -657,27 +733,51 @@ hipError_t launch_step_kernel(K kernel, int32_t nblk, const StepArgs& s, hipStre
   return hipGetLastError();
 }
 
-// The two launches of a panel half-step; with events, the start event takes
-// the first kernel's start and the stop event the second kernel's end.
+// The launches of a panel half-step: dense tiles and their group sums (if
+// dense rows), the long rows' panel dots (if long rows), then the row
+// updates.  With events, the start event takes the first kernel's start and
+// the stop event the last kernel's end.
 template <typename T, typename KD, typename AD>
-hipError_t launch_panel_pair(hlp_lp* lp, const T* pval, const T* vec, KD kdual, const AD& ad, const StepArgs& s) {
-  PanelDotArgs<T> pa{reinterpret_cast<const int4*>(lp->tabP), lp->pp, lp->pcol, pval, vec,
-                     reinterpret_cast<T*>(lp->ppart), {}};
-  for (int k = 0; k < 9; ++k) pa.off[k] = lp->poff[k];
-  StepArgs s1 = s, s2 = s;
-  s1.ev_stop = nullptr;
-  s2.ev_start = nullptr;
-  hipError_t e = lp->nt ? launch_step_kernel(k_panel_dot<T, true>, lp->nbPgrid, s1, lp->stream, pa)
-                        : launch_step_kernel(k_panel_dot<T, false>, lp->nbPgrid, s1, lp->stream, pa);
-  if (e != hipSuccess) return e;
-  return launch_step_kernel(kdual, lp->nbS + lp->nbC, s2, lp->stream, ad);
+hipError_t launch_panel_dual(hlp_lp* lp, const T* pval, const T* pvalD, const T* vec, KD kdual, const AD& ad,
+                             const StepArgs& s) {
+  StepArgs first = s, mid = s, last = s;
+  first.ev_stop = nullptr;
+  mid.ev_start = mid.ev_stop = nullptr;
+  last.ev_start = nullptr;
+  bool started = false;
+  auto take = [&]() -> const StepArgs& {
+    const StepArgs& a = started ? mid : first;
+    started = true;
+    return a;
+  };
+  hipError_t e;
+  if (lp->nD > 0) {
+    DenseDotArgs<T> da{reinterpret_cast<const int4*>(lp->tilesD), reinterpret_cast<const int4*>(lp->rbxD), lp->ppD,
+                       lp->pcolD, pvalD, vec, reinterpret_cast<T*>(lp->partD), lp->n};
+    e = lp->nt ? launch_step_kernel(k_dense_dot<T, true>, lp->ntilesD, take(), lp->stream, da)
+               : launch_step_kernel(k_dense_dot<T, false>, lp->ntilesD, take(), lp->stream, da);
+    if (e != hipSuccess) return e;
+    const int32_t G = (lp->dense_P + kDenseGroup - 1) / kDenseGroup;
+    hipLaunchKernelGGL(k_dense_combine<T>, dim3(lp->nbCD, G), dim3(kBlock), 0, lp->stream,
+                       reinterpret_cast<const T*>(lp->partD), lp->nD, lp->dense_P, reinterpret_cast<T*>(lp->part2D));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (lp->nL > 0) {
+    PanelDotArgs<T> pa{reinterpret_cast<const int4*>(lp->tabP), lp->pp, lp->pcol, pval, vec,
+                       reinterpret_cast<T*>(lp->ppart), {}};
+    for (int k = 0; k < 9; ++k) pa.off[k] = lp->poff[k];
+    e = lp->nt ? launch_step_kernel(k_panel_dot<T, true>, lp->nbPgrid, take(), lp->stream, pa)
+               : launch_step_kernel(k_panel_dot<T, false>, lp->nbPgrid, take(), lp->stream, pa);
+    if (e != hipSuccess) return e;
+  }
+  return launch_step_kernel(kdual, lp->nbS + lp->nbC + lp->nbCD, started ? last : s, lp->stream, ad);
 }
 
 template <typename T>
 hipError_t refresh_long_y(hlp_lp* lp, T* y) {
-  if (!lp->panels || lp->nL == 0 || !y) return hipSuccess;
-  hipLaunchKernelGGL(k_refresh_long_y<T>, dim3(nblocks(lp->nL)), dim3(kBlock), 0, lp->stream, y, lp->lrow, lp->nL,
-                     lp->m);
+  const int32_t nc = lp->nL + lp->nD;  // long rows, then dense rows
+  if (!lp->panels || nc == 0 || !y) return hipSuccess;
+  hipLaunchKernelGGL(k_refresh_long_y<T>, dim3(nblocks(nc)), dim3(kBlock), 0, lp->stream, y, lp->lrow, nc, lp->m);
   return hipGetLastError();
 }
 
@@ -710,11 +810,12 @@ hipError_t launch_dual(hlp_lp* lp, const StepArgs& s) {
     return e != hipSuccess ? e : refresh_long_y(lp, lp->y);
   }
   if (lp->panels) {
+    const int32_t G = (lp->dense_P + kDenseGroup - 1) / kDenseGroup;
     DualPanelArgs d{reinterpret_cast<const int4*>(lp->rbxS), lp->sp, lp->scol, lp->sval, lp->xbar, lp->y, lp->ya,
-                    lp->lct, lp->uct, lp->step, lp->lbits, lp->lrow, lp->ppart, lp->panels, lp->nL, lp->nbS, s.j,
-                    lp->m};
-    return lp->nt ? launch_panel_pair<double>(lp, lp->pval, lp->xbar, k_dual_pn<true>, d, s)
-                  : launch_panel_pair<double>(lp, lp->pval, lp->xbar, k_dual_pn<false>, d, s);
+                    lp->lct, lp->uct, lp->step, lp->lbits, lp->lrow, lp->ppart, lp->part2D, lp->panels, lp->nL,
+                    lp->nbS, s.j, lp->m, lp->nbC, lp->nD, G};
+    return lp->nt ? launch_panel_dual<double>(lp, lp->pval, lp->pvalD, lp->xbar, k_dual_pn<true>, d, s)
+                  : launch_panel_dual<double>(lp, lp->pval, lp->pvalD, lp->xbar, k_dual_pn<false>, d, s);
   }
   if (lp->nt) return launch_step_kernel(k_dual<0, true>, lp->nbA, s, lp->stream, a);
   return launch_step_kernel(k_dual<0, false>, lp->nbA, s, lp->stream, a);
@@ -840,11 +941,13 @@ hipError_t launch_dual32(hlp_lp* lp, const StepArgs& s) {
   }
   if (lp->panels) {
     const float* part = reinterpret_cast<const float*>(lp->ppart);
+    const float* part2 = reinterpret_cast<const float*>(lp->part2D);
+    const int32_t G = (lp->dense_P + kDenseGroup - 1) / kDenseGroup;
     Dual32PanelArgs d{reinterpret_cast<const int4*>(lp->rbxS), lp->sp, lp->scol, lp->sval32, lp->xbar32, lp->y32,
-                      lp->ya32, lp->lc32, lp->uc32, lp->b32, lp->step, lp->lbits, lp->lrow, part, lp->panels, lp->nL,
-                      lp->nbS, s.j, lp->m};
-    return lp->nt ? launch_panel_pair<float>(lp, lp->pval32, lp->xbar32, k_dual32_pn<true>, d, s)
-                  : launch_panel_pair<float>(lp, lp->pval32, lp->xbar32, k_dual32_pn<false>, d, s);
+                      lp->ya32, lp->lc32, lp->uc32, lp->b32, lp->step, lp->lbits, lp->lrow, part, part2, lp->panels,
+                      lp->nL, lp->nbS, s.j, lp->m, lp->nbC, lp->nD, G};
+    return lp->nt ? launch_panel_dual<float>(lp, lp->pval32, lp->pval32D, lp->xbar32, k_dual32_pn<true>, d, s)
+                  : launch_panel_dual<float>(lp, lp->pval32, lp->pval32D, lp->xbar32, k_dual32_pn<false>, d, s);
   }
   if (lp->nt) return launch_step_kernel(k_dual32<false, true>, lp->nbA, s, lp->stream, a);
   return launch_step_kernel(k_dual32<false, false>, lp->nbA, s, lp->stream, a);

@@ -303,40 +303,50 @@ __global__ void k_rb_expand(const int32_t* __restrict__ rb, const int32_t* __res
 }
 
 // ----------------------------------------------------------------- column panels
-// Long rows (more than T nonzeros): fl[i] = 1; the short part keeps the other
-// rows' lengths.  Both arrays get a terminal 0 so their exclusive scans end
-// with the totals.
-__global__ void k_pn_flags(const int32_t* __restrict__ rp, int32_t m, int32_t T, int32_t* __restrict__ fl,
-                           int32_t* __restrict__ slen) {
+// Row classes: short (at most T nonzeros), long (more than T, below Ld) and,
+// with Ld > 0, dense (at least Ld).  fl / fd flag the long / dense rows; the
+// short part keeps the short rows' lengths.  All three get a terminal 0 so
+// their exclusive scans end with the totals.
+__global__ void k_pn_flags(const int32_t* __restrict__ rp, int32_t m, int32_t T, int32_t Ld,
+                           int32_t* __restrict__ fl, int32_t* __restrict__ fd, int32_t* __restrict__ slen) {
   int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i > m) return;
   if (i == m) {
     fl[m] = 0;
+    fd[m] = 0;
     slen[m] = 0;
     return;
   }
   const int len = rp[i + 1] - rp[i];
-  const int lg = len > T;
+  const int dense = Ld > 0 && len >= Ld;
+  const int lg = len > T && !dense;
   fl[i] = lg;
-  slen[i] = lg ? 0 : len;
+  fd[i] = dense;
+  slen[i] = (lg || dense) ? 0 : len;
 }
 
-__global__ void k_pn_counts(const int32_t* __restrict__ plid, const int32_t* __restrict__ sp, int32_t m,
-                            int32_t* __restrict__ counts) {
+__global__ void k_pn_counts(const int32_t* __restrict__ plid, const int32_t* __restrict__ sp,
+                            const int32_t* __restrict__ dlid, int32_t m, int32_t* __restrict__ counts) {
   counts[0] = plid[m];
   counts[1] = sp[m];
+  counts[2] = dlid[m];
 }
 
-// Short rows copied into AS (in order); long rows listed in lrow.
+// Short rows copied into AS (in order); long rows listed in lrow[0, nL),
+// dense rows in lrow[nL, nL + nD).
 __global__ void k_pn_short(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                            const double* __restrict__ val, const float* __restrict__ val32,
-                           const int32_t* __restrict__ plid, const int32_t* __restrict__ sp, int32_t m,
-                           int32_t* __restrict__ scol, double* __restrict__ sval, float* __restrict__ sval32,
-                           int32_t* __restrict__ lrow) {
+                           const int32_t* __restrict__ plid, const int32_t* __restrict__ dlid,
+                           const int32_t* __restrict__ sp, int32_t m, int32_t nL, int32_t* __restrict__ scol,
+                           double* __restrict__ sval, float* __restrict__ sval32, int32_t* __restrict__ lrow) {
   int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= m) return;
   if (plid[i + 1] != plid[i]) {
     lrow[plid[i]] = (int32_t)i;
+    return;
+  }
+  if (dlid[i + 1] != dlid[i]) {
+    lrow[nL + dlid[i]] = (int32_t)i;
     return;
   }
   const int b = rp[i], d = sp[i] - b;
@@ -347,18 +357,19 @@ __global__ void k_pn_short(const int32_t* __restrict__ rp, const int32_t* __rest
   }
 }
 
-__global__ void k_pn_bits(const int32_t* __restrict__ plid, int32_t m, uint32_t* __restrict__ bits) {
+// bit i: row i is long or dense (its update comes from panel sums)
+__global__ void k_pn_bits(const int32_t* __restrict__ plid, const int32_t* __restrict__ dlid, int32_t m,
+                          uint32_t* __restrict__ bits) {
   int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (w >= ((int64_t)m + 31) / 32) return;
   uint32_t b = 0;
   for (int k = 0; k < 32; ++k) {
     const int64_t i = w * 32 + k;
-    if (i < m && plid[i + 1] != plid[i]) b |= 1u << k;
+    if (i < m && (plid[i + 1] != plid[i] || dlid[i + 1] != dlid[i])) b |= 1u << k;
   }
   bits[w] = b;
 }
 
-// first position q in [lo, hi) with col[q] >= c (columns increase within a row)
 __device__ int lower_col(const int32_t* __restrict__ col, int lo, int hi, int64_t c) {
   while (lo < hi) {
     const int mid = lo + (hi - lo) / 2;
@@ -407,13 +418,16 @@ __global__ void k_pn_long(const int32_t* __restrict__ rp, const int32_t* __restr
   }
 }
 
-__global__ void k_pn_remap(const int32_t* __restrict__ row, const int32_t* __restrict__ plid, int32_t m,
-                           int64_t nnz, int32_t* __restrict__ rowc) {
+// A~^T's row indices with long and dense rows redirected to their entries of
+// the compact copy of y (m + l, m + nL + d).
+__global__ void k_pn_remap(const int32_t* __restrict__ row, const int32_t* __restrict__ plid,
+                           const int32_t* __restrict__ dlid, int32_t m, int32_t nL, int64_t nnz,
+                           int32_t* __restrict__ rowc) {
   int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (q >= nnz) return;
   const int i = row[q];
-  const int l = plid[i];
-  rowc[q] = plid[i + 1] != l ? m + l : i;
+  const int l = plid[i], d = dlid[i];
+  rowc[q] = plid[i + 1] != l ? m + l : (dlid[i + 1] != d ? m + nL + d : i);
 }
 
 // First block of each panel (panels start blocks: see k_rb_flags).
@@ -750,54 +764,83 @@ hipError_t launch_build_row_blocks(hlp_lp* lp, const int32_t* ptr, int32_t rows,
   return hipGetLastError();
 }
 
-hipError_t launch_panel_split(hlp_lp* lp, int32_t T, int32_t* counts) {
+hipError_t launch_panel_split(hlp_lp* lp, int32_t T, int32_t Ld, int32_t* counts) {
   hipStream_t s = lp->stream;
   const int32_t m = lp->m;
-  hipLaunchKernelGGL(k_pn_flags, dim3(nblocks((int64_t)m + 1)), dim3(kBlock), 0, s, lp->rp, m, T, lp->pscrA,
-                     lp->pscrB);
+  hipLaunchKernelGGL(k_pn_flags, dim3(nblocks((int64_t)m + 1)), dim3(kBlock), 0, s, lp->rp, m, T, Ld, lp->pscrA,
+                     lp->pscrC, lp->pscrB);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if ((e = scan_exclusive(lp->pscrA, lp->plid, (int64_t)m + 1, lp->scan_tmp, s)) != hipSuccess) return e;
+  if ((e = scan_exclusive(lp->pscrC, lp->dlid, (int64_t)m + 1, lp->scan_tmp, s)) != hipSuccess) return e;
   if ((e = scan_exclusive(lp->pscrB, lp->sp, (int64_t)m + 1, lp->scan_tmp, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pn_counts, dim3(1), dim3(1), 0, s, lp->plid, lp->sp, m, counts);
+  hipLaunchKernelGGL(k_pn_counts, dim3(1), dim3(1), 0, s, lp->plid, lp->sp, lp->dlid, m, counts);
   return hipGetLastError();
 }
 
-// Needs lp->panels, panel_w and nL set (nL <= nL_cap); block counts of AS and
-// AP go to counts[2] and counts[3].
-hipError_t launch_panel_layout(hlp_lp* lp, int32_t* counts) {
+namespace {
+// Panel-major copy of the rows lrow[0, nrows): segment t = p*nrows + l, its
+// row pointers pp (via the scratch arrays), then the nonzeros.
+hipError_t panel_copy(hlp_lp* lp, const int32_t* rows, int32_t nrows, int32_t P, int32_t W, int32_t* pp,
+                      int32_t* pcol, double* pval, float* pval32) {
   hipStream_t s = lp->stream;
-  const int32_t m = lp->m, nL = lp->nL, P = lp->panels, W = lp->panel_w;
-  const int64_t R = (int64_t)P * nL;
-  if (nL < 1 || nL > lp->nL_cap || R + 1 > lp->rbtmp_rows + 1) return hipErrorInvalidValue;
+  const int64_t R = (int64_t)P * nrows;
+  if (nrows < 1 || R + 1 > lp->rbtmp_rows + 1) return hipErrorInvalidValue;
   const float* v32 = lp->precision == HLP_MIXED ? lp->val32 : nullptr;
-  hipLaunchKernelGGL(k_pn_short, dim3(nblocks(m)), dim3(kBlock), 0, s, lp->rp, lp->col, lp->val, v32, lp->plid,
-                     lp->sp, m, lp->scol, lp->sval, lp->sval32, lp->lrow);
-  hipLaunchKernelGGL(k_pn_bits, dim3(nblocks(((int64_t)m + 31) / 32)), dim3(kBlock), 0, s, lp->plid, m,
-                     lp->lbits);
-  hipLaunchKernelGGL(k_pn_seg, dim3(nblocks(R + 1)), dim3(kBlock), 0, s, lp->rp, lp->col, lp->lrow, nL, P, W,
+  hipLaunchKernelGGL(k_pn_seg, dim3(nblocks(R + 1)), dim3(kBlock), 0, s, lp->rp, lp->col, rows, nrows, P, W,
                      lp->pscrA, lp->pscrB);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if ((e = scan_exclusive(lp->pscrA, lp->pp, R + 1, lp->scan_tmp, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pn_long, dim3(nL), dim3(kBlock), 0, s, lp->rp, lp->col, lp->val, v32, lp->lrow, nL, W,
-                     lp->pp, lp->pscrB, lp->pcol, lp->pval, lp->pval32);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = launch_build_row_blocks(lp, lp->sp, m, lp->rbS, lp->rbxS, counts + 2)) != hipSuccess) return e;
-  return launch_build_row_blocks(lp, lp->pp, (int32_t)R, lp->rbP, lp->rbxP, counts + 3, nL);
+  if ((e = scan_exclusive(lp->pscrA, pp, R + 1, lp->scan_tmp, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pn_long, dim3(nrows), dim3(kBlock), 0, s, lp->rp, lp->col, lp->val, v32, rows, nrows, W,
+                     pp, lp->pscrB, pcol, pval, v32 ? pval32 : nullptr);
+  return hipGetLastError();
+}
+}  // namespace
+
+// Needs lp->panels, panel_w, nL, nD (and dense_P, dense_w if nD > 0) set.
+hipError_t launch_panel_layout(hlp_lp* lp, int32_t* counts) {
+  hipStream_t s = lp->stream;
+  const int32_t m = lp->m, nL = lp->nL, nD = lp->nD;
+  if (nL < 0 || nD < 0 || nL + nD < 1 || nL + nD > lp->nL_cap || nD > lp->nD_cap) return hipErrorInvalidValue;
+  const float* v32 = lp->precision == HLP_MIXED ? lp->val32 : nullptr;
+  hipLaunchKernelGGL(k_pn_short, dim3(nblocks(m)), dim3(kBlock), 0, s, lp->rp, lp->col, lp->val, v32, lp->plid,
+                     lp->dlid, lp->sp, m, nL, lp->scol, lp->sval, lp->sval32, lp->lrow);
+  hipLaunchKernelGGL(k_pn_bits, dim3(nblocks(((int64_t)m + 31) / 32)), dim3(kBlock), 0, s, lp->plid, lp->dlid, m,
+                     lp->lbits);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = launch_build_row_blocks(lp, lp->sp, m, lp->rbS, lp->rbxS, counts + 3)) != hipSuccess) return e;
+  if (nL > 0) {
+    if ((e = panel_copy(lp, lp->lrow, nL, lp->panels, lp->panel_w, lp->pp, lp->pcol, lp->pval, lp->pval32)) !=
+        hipSuccess)
+      return e;
+    const int64_t R = (int64_t)lp->panels * nL;
+    if ((e = launch_build_row_blocks(lp, lp->pp, (int32_t)R, lp->rbP, lp->rbxP, counts + 4, nL)) != hipSuccess)
+      return e;
+  }
+  if (nD > 0) {
+    if ((e = panel_copy(lp, lp->lrow + nL, nD, lp->dense_P, lp->dense_w, lp->ppD, lp->pcolD, lp->pvalD,
+                        lp->pval32D)) != hipSuccess)
+      return e;
+    const int64_t RD = (int64_t)lp->dense_P * nD;
+    if ((e = launch_build_row_blocks(lp, lp->ppD, (int32_t)RD, lp->rbD, lp->rbxD, counts + 5, nD)) != hipSuccess)
+      return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_panel_remap(hlp_lp* lp) {
   if (lp->nnz == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pn_remap, dim3(nblocks(lp->nnz)), dim3(kBlock), 0, lp->stream, lp->row, lp->plid, lp->m,
-                     lp->nnz, lp->rowc);
+  hipLaunchKernelGGL(k_pn_remap, dim3(nblocks(lp->nnz)), dim3(kBlock), 0, lp->stream, lp->row, lp->plid, lp->dlid,
+                     lp->m, lp->nL, lp->nnz, lp->rowc);
   return hipGetLastError();
 }
 
-hipError_t launch_panel_starts(hlp_lp* lp, int32_t* pstart) {
-  if (lp->nbP < 1 || lp->nL < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_pn_starts, dim3(nblocks(lp->nbP)), dim3(kBlock), 0, lp->stream, lp->rbxP, lp->nbP, lp->nL,
-                     pstart);
+hipError_t launch_panel_starts(const int32_t* rbx, int32_t nb, int32_t rows_per_panel, int32_t* pstart,
+                               hipStream_t s) {
+  if (nb < 1 || rows_per_panel < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pn_starts, dim3(nblocks(nb)), dim3(kBlock), 0, s, rbx, nb, rows_per_panel, pstart);
   return hipGetLastError();
 }
 

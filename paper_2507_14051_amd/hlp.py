@@ -34,6 +34,7 @@ class HlpParams(C.Structure):
         ("restart_to_current", C.c_int32), ("power_tol", C.c_double), ("pid_min_norm", C.c_double),
         ("trace_iters", C.c_int32), ("debug_poison_iter", C.c_int32), ("graphs", C.c_int32),
         ("stream_matrix", C.c_int32), ("column_panels", C.c_int32), ("panel_row_min", C.c_int32),
+        ("dense_row_min", C.c_int32),
     ]
 
 
@@ -74,7 +75,7 @@ def lib():
         L.hlp_solve.argtypes = [P, C.POINTER(HlpParams), P, P, P, P, P, C.POINTER(HlpInfo), P]
         L.hlp_lp_scaling.argtypes = [P, P, P, C.POINTER(C.c_double), C.POINTER(I32)]
         L.hlp_lp_transpose.argtypes = [P, P, P, P]
-        L.hlp_lp_panels.argtypes = [P, C.POINTER(I32), C.POINTER(I32)]
+        L.hlp_lp_panels.argtypes = [P] + [C.POINTER(I32)] * 4
         L.hlp_tape_bytes.argtypes = [P, I32, I32, C.POINTER(SZ)]
         L.hlp_unrolled_forward.argtypes = [P, C.POINTER(HlpParams), I32, I32, I32, P, P, P, P, P, SZ]
         L.hlp_unrolled_backward.argtypes = [P, P, SZ] + [P] * 7
@@ -153,9 +154,10 @@ def hlp_lp_scaling(lp, d_r=None, d_c=None):
 
 
 def hlp_lp_panels(lp):
-    P, nl = C.c_int32(0), C.c_int32(0)
-    _check(lib().hlp_lp_panels(lp, C.byref(P), C.byref(nl)))
-    return P.value, nl.value
+    """(panels, long rows, dense panels, dense rows)."""
+    v = [C.c_int32(0) for _ in range(4)]
+    _check(lib().hlp_lp_panels(lp, *[C.byref(x) for x in v]))
+    return tuple(x.value for x in v)
 
 
 def hlp_lp_transpose(lp, col_ptr=None, row_idx=None, val=None):

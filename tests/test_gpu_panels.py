@@ -52,12 +52,16 @@ def _random_rows(rng, m, n, lengths):
     return sp.csr_matrix((rng.standard_normal(r.size), (r, c)), shape=(m, n))
 
 
-def _end_point_case(lp, K, panels, row_min):
+def _end_point_case(lp, K, panels, row_min, dense_min=4096):
     eta = oracle_eta(lp)
-    prob = problem(lp, eta=eta, column_panels=panels, panel_row_min=row_min)
+    prob = problem(lp, eta=eta, column_panels=panels, panel_row_min=row_min, dense_row_min=dense_min)
     P, nl = prob.panels()
+    PD, nd = prob.dense()
     lens = np.diff(lp.A.indptr)
-    assert P == 8 * ((panels + 7) // 8) and nl == int((lens > row_min).sum()) > 0
+    dense = (lens >= dense_min) if dense_min else np.zeros(lens.size, bool)
+    assert P == 8 * ((panels + 7) // 8)
+    assert nl == int(((lens > row_min) & ~dense).sum()) and nd == int(dense.sum()) and nl + nd > 0
+    assert PD == (-(-lp.n // 2048) if nd else 0)
     out = np_out(prob.solve(tol=0.0, max_iter=K))
     prob.close()
     plain = problem(lp, eta=eta, column_panels=0)
@@ -67,7 +71,7 @@ def _end_point_case(lp, K, panels, row_min):
     ref = oracle.solve(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, Params(tol=0.0, max_iter=K, eta_override=eta))
     ex, ey = rel(out["x"], ref.x), rel(out["y"], ref.y)
     gx, gy = rel(out["x"], ref_gpu["x"]), rel(out["y"], ref_gpu["y"])
-    print(f"K={K} P={P} long rows={nl}: vs oracle {ex:.1e} {ey:.1e}; vs unsplit {gx:.1e} {gy:.1e}")
+    print(f"K={K} P={P} long rows={nl} dense rows={nd}: vs oracle {ex:.1e} {ey:.1e}; vs unsplit {gx:.1e} {gy:.1e}")
     assert ex <= TOL and ey <= TOL
     assert gx <= 1e-12 and gy <= 1e-12
     assert out["info"]["restarts"] == ref.restarts
@@ -82,6 +86,34 @@ def test_panels_skewed_rows_match_oracle(K):
     lp = lpgen.gen(3000, 20000, zipf_alpha=1.3, cap=9000, eq_frac=0.3, free_frac=0.2, values="normal", seed=7)
     announce(f"panels skewed K={K} nnz={lp.nnz}")
     _end_point_case(lp, K, panels=16, row_min=8)
+
+
+@pytest.mark.parametrize("dense_min", [0, 512])
+def test_panels_long_and_dense_rows(dense_min):
+    """Rows above 512 nonzeros in the narrow LDS-staged panels, the rest of the
+    long rows in the wide panels; and the same LP with no dense class."""
+    lp = lpgen.gen(3000, 20000, zipf_alpha=1.3, cap=9000, eq_frac=0.3, free_frac=0.2, values="normal", seed=7)
+    announce(f"panels long + dense ({dense_min}) nnz={lp.nnz}")
+    _end_point_case(lp, 200, panels=16, row_min=8, dense_min=dense_min)
+
+
+def test_panels_only_dense_rows():
+    """Every row above panel_row_min is dense: the wide panels are empty."""
+    lp = lpgen.config("c1", seed=2)
+    announce("panels only dense rows (c1)")
+    _end_point_case(lp, 200, panels=8, row_min=2, dense_min=3)
+
+
+def test_panels_dense_rows_wider_than_one_narrow_panel():
+    """n = 9,000 (five narrow panels, the last one partial); dense rows of
+    2,000-8,000 nonzeros next to short ones."""
+    rng = np.random.default_rng(12)
+    m, n = 400, 9000
+    lens = rng.integers(0, 8, size=m)
+    lens[::50] = rng.integers(2000, 8000, size=lens[::50].size)
+    lp = _lp_from_matrix(_random_rows(rng, m, n, lens), seed=12)
+    announce(f"panels dense partial narrow panel nnz={lp.nnz}")
+    _end_point_case(lp, 130, panels=8, row_min=16, dense_min=1000)
 
 
 def test_panels_all_rows_long():
@@ -116,8 +148,8 @@ def test_panels_fp64_solve_to_tolerance_and_repeatable():
     lp = lpgen.config("c1", seed=3)
     announce("panels c1 solve 1e-8")
     eta = oracle_eta(lp)
-    prob = problem(lp, eta=eta, column_panels=8, panel_row_min=3)
-    assert prob.panels()[0] == 8
+    prob = problem(lp, eta=eta, column_panels=8, panel_row_min=3, dense_row_min=5)
+    assert prob.panels()[0] == 8 and prob.dense()[1] > 0
     a = np_out(prob.solve(tol=1e-8))
     b = np_out(prob.solve(tol=1e-8))
     c = np_out(prob.solve(tol=1e-8, graphs=0))
@@ -133,13 +165,13 @@ def test_panels_fp64_solve_to_tolerance_and_repeatable():
 
 
 def test_panels_mixed_precision():
-    """FP32 panel path: same tolerance by the oracle's KKT; graphs bitwise equal
-    to direct launches; close to the unsplit FP32 path."""
+    """FP32 panel path (wide and narrow panels): same tolerance by the oracle's
+    KKT; graphs bitwise equal to direct launches; close to the unsplit FP32 path."""
     from paper_2507_14051_amd import MIXED
     lp = lpgen.gen(3000, 20000, zipf_alpha=1.3, cap=9000, eq_frac=0.3, free_frac=0.2, values="normal", seed=7)
     announce("panels mixed")
-    prob = problem(lp, precision=MIXED, column_panels=16, panel_row_min=8)
-    assert prob.panels()[0] == 16
+    prob = problem(lp, precision=MIXED, column_panels=16, panel_row_min=8, dense_row_min=512)
+    assert prob.panels()[0] == 16 and prob.dense()[1] > 0
     a = np_out(prob.solve(tol=0.0, max_iter=300))
     b = np_out(prob.solve(tol=0.0, max_iter=300, graphs=0))
     prob.close()
@@ -150,7 +182,7 @@ def test_panels_mixed_precision():
     print(f"mixed panels vs unsplit after 300: x {rel(a['x'], c['x']):.1e} y {rel(a['y'], c['y']):.1e}")
     assert rel(a["x"], c["x"]) <= 1e-4 and rel(a["y"], c["y"]) <= 1e-4
     lp1 = lpgen.config("c1", seed=1)
-    p1 = problem(lp1, precision=MIXED, column_panels=8, panel_row_min=3)
+    p1 = problem(lp1, precision=MIXED, column_panels=8, panel_row_min=3, dense_row_min=5)
     o = np_out(p1.solve(tol=1e-8))
     p1.close()
     k = oracle.kkt(lp1.A, lp1.c, lp1.lc, lp1.uc, lp1.lv, lp1.uv, o["x"], o["y"])
@@ -164,7 +196,10 @@ def test_panels_automatic_on_large_skewed_lp():
     announce(f"panels c3b nnz={lp.nnz}")
     a = problem(lp)
     P, nl = a.panels()
-    assert P == 24 and nl == int((np.diff(lp.A.indptr) > 16).sum())
+    PD, nd = a.dense()
+    lens = np.diff(lp.A.indptr)
+    assert P == 24 and nl == int(((lens > 16) & (lens < 4096)).sum())
+    assert PD == 2442 and nd == int((lens >= 4096).sum()) > 0
     oa = np_out(a.solve(tol=0.0, max_iter=200))
     a.close()
     b = problem(lp, column_panels=0)
@@ -192,8 +227,8 @@ def test_panels_leave_adjoint_and_later_solves_unchanged():
     announce(f"panels adjoint nnz={lp.nnz}")
     rng = np.random.default_rng(4)
     gx = rng.standard_normal(lp.n); gy = rng.standard_normal(lp.m)
-    pa = problem(lp, column_panels=8, panel_row_min=8)
-    assert pa.panels()[0] == 8
+    pa = problem(lp, column_panels=8, panel_row_min=8, dense_row_min=400)
+    assert pa.panels()[0] == 8 and pa.dense()[1] > 0
     before = np_out(pa.solve(tol=0.0, max_iter=150))
     xa, ya, ga = _grads(pa, lp, 120, 25, gx, gy, eval_freq=16)
     after = np_out(pa.solve(tol=0.0, max_iter=150))
