@@ -90,16 +90,20 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
   L->nL_cap = (int32_t)nLmax;
   // dense rows (at least dense_row_min nonzeros): narrow panels of kDenseW columns
   int64_t nDmax = 0, RD = 0, PD = 0, GD = 0;
+  int64_t PT = 0, RT = 0;
   if (panels > 0 && dense_row_min > panel_row_min) {
     PD = ((int64_t)n + kDenseW - 1) / kDenseW;
     GD = (PD + kDenseGroup - 1) / kDenseGroup;
-    nDmax = std::min<int64_t>(m, nnz / dense_row_min);
+    nDmax = std::min<int64_t>(std::min<int64_t>(m, nnz / dense_row_min), kMaxDense);
     RD = PD * nDmax;
-    if (RD + PD + 2 >= (int64_t(1) << 30)) nDmax = RD = 0;
+    PT = (nDmax + kDenseW - 1) / kDenseW;
+    RT = PT * n;
+    if (nDmax == 0 || RD + PD + 2 >= (int64_t(1) << 30) || RT + PT + 2 >= (int64_t(1) << 30)) nDmax = RD = PT = RT = 0;
   }
   L->nD_cap = (int32_t)nDmax;
   L->dense_P = (int32_t)PD;
-  const int64_t RB = std::max<int64_t>(N, std::max(R, RD));
+  L->dense_PT_cap = (int32_t)PT;
+  const int64_t RB = std::max<int64_t>(std::max<int64_t>(N, R), std::max(RD, RT));
   L->rp = c.take<int32_t>((int64_t)m + 1);
   L->col = c.take<int32_t>(nnz);
   L->val0 = c.take<double>(nnz);
@@ -207,9 +211,27 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
     L->pval32D = mixed ? c.take<float>(nnz) : nullptr;
     L->partD = c.take<double>(RD);
     L->part2D = c.take<double>(GD * nDmax);
+    const int64_t bD = std::min<int64_t>(RD, row_block_bound(RD, nnz, PD));
     L->rbD = c.take<int32_t>(RD + 2);
-    L->rbxD = c.take<int32_t>(4 * (RD + 1));
-    L->tilesD = c.take<int32_t>(4 * (RD + PD + 1));
+    L->capD_blocks = bD + 1;
+    L->rbxD = c.take<int32_t>(4 * (bD + 1));
+    L->tilesD = c.take<int32_t>(4 * (bD + 1));
+    L->cpR = c.take<int32_t>((int64_t)n + 1);
+    L->rowR = c.take<int32_t>(nnz);
+    L->tvalR = c.take<double>(nnz);
+    L->tval32R = mixed ? c.take<float>(nnz) : nullptr;
+    L->ppT = c.take<int32_t>(RT + 1);
+    L->rowT = c.take<int32_t>(nnz);
+    L->tvalT = c.take<double>(nnz);
+    L->tval32T = mixed ? c.take<float>(nnz) : nullptr;
+    L->partT = c.take<double>(RT);
+    const int64_t bT = std::min<int64_t>(RT, row_block_bound(RT, nnz, PT));
+    L->rbR = c.take<int32_t>((int64_t)n + 2);
+    L->rbxR = c.take<int32_t>(4 * ((int64_t)n + 1));
+    L->rbT2 = c.take<int32_t>(RT + 2);
+    L->capT_blocks = bT + 1;
+    L->rbxT2 = c.take<int32_t>(4 * (bT + 1));
+    L->tilesT = c.take<int32_t>(4 * (bT + 1));
   }
   // power iteration vectors alias iteration buffers (setup only)
   L->pv = L->rbuf;
@@ -337,6 +359,10 @@ static hlp_err build_panels(hlp_lp* lp, int32_t P, int32_t T, int32_t Ld, bool a
   lp->nbS = cnt[3];
   lp->nbP = nL > 0 ? cnt[4] : 0;
   lp->nbD = nD > 0 ? cnt[5] : 0;
+  if (lp->nbD > lp->capD_blocks) {
+    set_error("dense panels: more row blocks than reserved");
+    return HLP_EUNSUPPORTED;
+  }
   HLP_HIP(launch_panel_remap(lp));
   std::vector<int32_t> pstart;
   lp->nbPgrid = 0;
@@ -363,7 +389,8 @@ static hlp_err build_panels(hlp_lp* lp, int32_t P, int32_t T, int32_t Ld, bool a
     lp->nbPgrid = 8 * widest;
   }
   lp->nbC = (nL + 255) / 256;
-  lp->ntilesD = 0;
+  lp->ntilesD = lp->ntilesT = 0;
+  lp->dense_PT = 0;
   lp->nbCD = (nD + 255) / 256;
   if (nD > 0) {
     // tiles: up to kTileBlocks consecutive row blocks of one narrow panel
@@ -377,11 +404,48 @@ static hlp_err build_panels(hlp_lp* lp, int32_t P, int32_t T, int32_t Ld, bool a
         tiles.push_back(0);
       }
     lp->ntilesD = (int32_t)(tiles.size() / 4);
-    if ((int64_t)lp->ntilesD > (int64_t)lp->dense_P * lp->nD_cap + lp->dense_P + 1) {
+    if ((int64_t)lp->ntilesD > lp->capD_blocks) {
       set_error("dense panels: tile table overflow");
       return HLP_EUNSUPPORTED;
     }
     HLP_HIP(hipMemcpyAsync(lp->tilesD, tiles.data(), tiles.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                           lp->stream));
+    // the primal side (ATR and ATD, tiles of ATD), when the dense rows hold at
+    // least half of the nonzeros (below that, the split costs more than the
+    // LDS slices save)
+    int32_t nnzD = 0;
+    HLP_HIP(hipMemcpyAsync(&nnzD, lp->ppD + (int64_t)lp->dense_P * nD, sizeof(int32_t), hipMemcpyDeviceToHost,
+                           lp->stream));
+    HLP_HIP(hipStreamSynchronize(lp->stream));
+    if (2 * (int64_t)nnzD < lp->nnz) {
+      HLP_HIP(hipStreamSynchronize(lp->stream));
+      return HLP_OK;
+    }
+    lp->dense_PT = (nD + lp->dense_w - 1) / lp->dense_w;
+    HLP_HIP(launch_dense_transpose(lp, lp->flags));
+    HLP_HIP(hipMemcpyAsync(cnt, lp->flags, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, lp->stream));
+    HLP_HIP(hipStreamSynchronize(lp->stream));
+    lp->nbR = cnt[6];
+    lp->nbT2 = cnt[7];
+    if (lp->nbT2 > lp->capT_blocks) {
+      set_error("dense panels: more row blocks than reserved");
+      return HLP_EUNSUPPORTED;
+    }
+    HLP_TRY(panel_starts(lp, lp->rbxT2, lp->nbT2, lp->n, lp->dense_PT, pstart));
+    tiles.clear();
+    for (int32_t r = 0; r < lp->dense_PT; ++r)
+      for (int32_t b = pstart[r]; b < pstart[r + 1]; b += kTileBlocks) {
+        tiles.push_back(b);
+        tiles.push_back(std::min(pstart[r + 1], b + kTileBlocks));
+        tiles.push_back(r);
+        tiles.push_back(0);
+      }
+    lp->ntilesT = (int32_t)(tiles.size() / 4);
+    if ((int64_t)lp->ntilesT > lp->capT_blocks) {
+      set_error("dense panels: tile table overflow");
+      return HLP_EUNSUPPORTED;
+    }
+    HLP_HIP(hipMemcpyAsync(lp->tilesT, tiles.data(), tiles.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                            lp->stream));
   }
   HLP_HIP(hipStreamSynchronize(lp->stream));

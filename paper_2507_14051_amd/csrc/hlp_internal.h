@@ -113,6 +113,18 @@ struct hlp_lp {
   double* part2D = nullptr;  // group sums of 64 narrow panels: ceil(dense_P / 64) * nD
   int32_t *rbD = nullptr, *rbxD = nullptr, *tilesD = nullptr;
   int32_t nbD = 0, ntilesD = 0, nbCD = 0;
+  // The primal side of the dense rows: ATR = A~^T without the dense rows'
+  // entries (indices remapped like rowc), ATD = those entries grouped by
+  // slices of dense_w entries of the compact copy of y (row r*n + j = the
+  // entries of column j whose dense index lies in slice r), with its tiles.
+  int32_t dense_PT = 0, dense_PT_cap = 0;
+  int32_t *cpR = nullptr, *rowR = nullptr, *ppT = nullptr, *rowT = nullptr;
+  double *tvalR = nullptr, *tvalT = nullptr;
+  float *tval32R = nullptr, *tval32T = nullptr;
+  double* partT = nullptr;  // dense_PT * n partial sums (float in the FP32 path)
+  int32_t *rbR = nullptr, *rbxR = nullptr, *rbT2 = nullptr, *rbxT2 = nullptr, *tilesT = nullptr;
+  int32_t nbR = 0, nbT2 = 0, ntilesT = 0;
+  int64_t capD_blocks = 0, capT_blocks = 0;  // row blocks (and tiles) reserved for AD and ATD
   int32_t nbS = 0, nbP = 0, nbPgrid = 0, nbC = 0;
   int32_t poff[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // blocks of XCD x: tabP[poff[x] .. poff[x+1])
   int64_t rbtmp_rows = 0;             // capacity of the row-block scratch (rows)
@@ -176,6 +188,12 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
 constexpr int32_t kDenseW = 2048;     // columns per narrow panel (its FP64 slice: 16 KB of LDS)
 constexpr int32_t kDenseGroup = 64;   // narrow panels summed per group
 constexpr int32_t kTileBlocks = 16;   // row blocks per tile
+constexpr int32_t kMaxDense = 65536;  // dense rows at most (more: no dense class)
+// Upper bound on the row blocks of a CSR with `rows` rows and nnz nonzeros
+// (see the row-block rules in device.h), with panels of `period` rows.
+inline int64_t row_block_bound(int64_t rows, int64_t nnz, int64_t panels) {
+  return rows / 256 + nnz / 2048 + 3 * (nnz / 65) + panels + 4;
+}
 // Panels reserved for these sizes and parameters (0: none).
 int32_t panel_count(int32_t n, const hlp_params* p);
 
@@ -210,8 +228,9 @@ struct StepArgs {
   uint8_t* mask_y = nullptr; // if set (FP64 only): write yhat and the clamp codes of w
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // if set: timestamps of the kernel itself
 };
+// rbx holds rbx_cap blocks (-1: one per row); the caller checks *count <= rbx_cap.
 hipError_t launch_build_row_blocks(hlp_lp* lp, const int32_t* ptr, int32_t rows, int32_t* rb, int32_t* rbx,
-                                   int32_t* count, int32_t period = 0);
+                                   int32_t* count, int32_t period = 0, int64_t rbx_cap = -1);
 // Column panels: long-row split (returns nL and the short-part nonzero count
 // through counts[0..1] on the device), then the panel layout and its blocks.
 // counts[0] = long rows, counts[1] = nonzeros of the short part, counts[2] = dense rows.
@@ -222,6 +241,8 @@ hipError_t launch_panel_layout(hlp_lp* lp, int32_t* counts);
 hipError_t launch_panel_starts(const int32_t* rbx, int32_t nb, int32_t rows_per_panel, int32_t* pstart,
                                hipStream_t s);
 hipError_t launch_panel_remap(hlp_lp* lp);
+// ATR and ATD (needs nD > 0, dense_PT set); block counts to counts[6], counts[7].
+hipError_t launch_dense_transpose(hlp_lp* lp, int32_t* counts);
 hipError_t launch_set_step(hlp_lp* lp, double tau, double sigma, double gamma, int64_t k0, double P = 1.0,
                            double D = 1.0);
 hipError_t launch_primal(hlp_lp* lp, const StepArgs& s);

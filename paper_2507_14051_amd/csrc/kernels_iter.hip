@@ -58,7 +58,17 @@ struct PrimalArgs {
   const double* y; double* x; const double* xa; const double* ct; const double* lv; const double* uv;
   double* xbar; double* xh; double* dx; double* partials; uint8_t* mask; const StepDev* step;
   int32_t j;
+  const double* partT;  // if PT > 0: the dense rows' part of A~^T y, PT slice sums per column
+  int32_t PT, n;
 };
+
+// The dense rows' part of column j's product: its slice sums in slice order.
+template <typename T>
+__device__ __forceinline__ T slice_sum(const T* __restrict__ partT, int32_t PT, int32_t n, int j) {
+  T h = T(0);
+  for (int r = 0; r < PT; ++r) h += partT[(int64_t)r * n + j];
+  return h;
+}
 
 // MODE 0: plain step; 1: also xhat, x - xhat and the check partials;
 // 2: also xhat and the clamp code of v (for the reverse mode).
@@ -77,7 +87,8 @@ __global__ __launch_bounds__(kBlock) void k_primal(PrimalArgs p) {
     xj = p.x[j]; cj = p.ct[j]; lo = p.lv[j]; hi = p.uv[j]; xaj = p.xa[j];
     a0 = p.cp[j]; a1 = p.cp[j + 1];
   }
-  const double g = rb_dot<double, NT>(p.row, p.tval, p.y, ps, pe, a0, a1, own, e - s, lds);
+  double g = rb_dot<double, NT>(p.row, p.tval, p.y, ps, pe, a0, a1, own, e - s, lds);
+  if (p.PT > 0 && own) g += slice_sum(p.partT, p.PT, p.n, j);
   double q0 = 0.0, q1 = 0.0;
   if (own) {
     const double tau = p.step->tau, gam = p.step->gamma, a = halpern_a(p.step, p.j);
@@ -469,6 +480,8 @@ struct Primal32Args {
   const float* y; float* x; const float* xa; const float* c; const float* lv; const float* uv;
   float* xbar; float* xh; float* dx; double* partials; const StepDev* step;
   int32_t j;
+  const float* partT;
+  int32_t PT, n;
 };
 
 template <bool RES, bool NT>
@@ -484,7 +497,8 @@ __global__ __launch_bounds__(kBlock) void k_primal32(Primal32Args p) {
     xj = p.x[j]; cj = p.c[j]; lo = p.lv[j]; hi = p.uv[j]; xaj = p.xa[j];
     a0 = p.cp[j]; a1 = p.cp[j + 1];
   }
-  const float g = rb_dot<float, NT>(p.row, p.tval, p.y, ps, pe, a0, a1, own, e - s, lds);
+  float g = rb_dot<float, NT>(p.row, p.tval, p.y, ps, pe, a0, a1, own, e - s, lds);
+  if (p.PT > 0 && own) g += slice_sum(p.partT, p.PT, p.n, j);
   double q0 = 0.0, q1 = 0.0;
   if (own) {
     const float tau = (float)p.step->tau, gam = (float)p.step->gamma, a = (float)halpern_a(p.step, p.j);
@@ -773,6 +787,22 @@ hipError_t launch_panel_dual(hlp_lp* lp, const T* pval, const T* pvalD, const T*
   return launch_step_kernel(kdual, lp->nbS + lp->nbC + lp->nbCD, started ? last : s, lp->stream, ad);
 }
 
+// The primal half-step with dense rows: the tiles of ATD (slices of the
+// compact copy of y in LDS) write the slice sums, then the row-block kernel
+// over ATR adds them.  Events as for launch_panel_dual.
+template <typename T, typename A, typename K>
+hipError_t launch_primal_pair(hlp_lp* lp, const T* tvalT, const T* y, const A& a, K kprimal, const StepArgs& s) {
+  StepArgs first = s, last = s;
+  first.ev_stop = nullptr;
+  last.ev_start = nullptr;
+  DenseDotArgs<T> da{reinterpret_cast<const int4*>(lp->tilesT), reinterpret_cast<const int4*>(lp->rbxT2), lp->ppT,
+                     lp->rowT, tvalT, y + lp->m + lp->nL, reinterpret_cast<T*>(lp->partT), lp->nD};
+  hipError_t e = lp->nt ? launch_step_kernel(k_dense_dot<T, true>, lp->ntilesT, first, lp->stream, da)
+                        : launch_step_kernel(k_dense_dot<T, false>, lp->ntilesT, first, lp->stream, da);
+  if (e != hipSuccess) return e;
+  return launch_step_kernel(kprimal, lp->nbR, last, lp->stream, a);
+}
+
 template <typename T>
 hipError_t refresh_long_y(hlp_lp* lp, T* y) {
   const int32_t nc = lp->nL + lp->nD;  // long rows, then dense rows
@@ -795,6 +825,17 @@ hipError_t launch_primal(hlp_lp* lp, const StepArgs& s) {
                lp->xbar, lp->xh, lp->dxv, region(lp, R_PRIMAL), s.mask_x, lp->step, s.j};
   if (s.mask_x) return launch_step_kernel(k_primal<2, false>, lp->nbT, s, lp->stream, a);
   if (s.residual) return launch_step_kernel(k_primal<1, false>, lp->nbT, s, lp->stream, a);
+  if (lp->panels && lp->ntilesT > 0) {
+    // dense rows' part first (slices of y staged in LDS), then the rest
+    a.rb = reinterpret_cast<const int4*>(lp->rbxR);
+    a.cp = lp->cpR;
+    a.row = lp->rowR;
+    a.tval = lp->tvalR;
+    a.partT = lp->partT;
+    a.PT = lp->dense_PT;
+    a.n = lp->n;
+    return launch_primal_pair(lp, lp->tvalT, lp->y, a, lp->nt ? k_primal<0, true> : k_primal<0, false>, s);
+  }
   if (lp->panels) a.row = lp->rowc;  // long rows' y entries from the compact copy
   if (lp->nt) return launch_step_kernel(k_primal<0, true>, lp->nbT, s, lp->stream, a);
   return launch_step_kernel(k_primal<0, false>, lp->nbT, s, lp->stream, a);
@@ -926,6 +967,17 @@ hipError_t launch_primal32(hlp_lp* lp, const StepArgs& s) {
   Primal32Args a{reinterpret_cast<const int4*>(lp->rbxT), lp->cp, lp->row, lp->tval32, lp->y32, lp->x32, lp->xa32, lp->c32, lp->lv32, lp->uv32,
                  lp->xbar32, lp->xh32, lp->dx32, region(lp, R_PRIMAL), lp->step, s.j};
   if (s.residual) return launch_step_kernel(k_primal32<true, false>, lp->nbT, s, lp->stream, a);
+  if (lp->panels && lp->ntilesT > 0) {
+    a.rb = reinterpret_cast<const int4*>(lp->rbxR);
+    a.cp = lp->cpR;
+    a.row = lp->rowR;
+    a.tval = lp->tval32R;
+    a.partT = reinterpret_cast<const float*>(lp->partT);
+    a.PT = lp->dense_PT;
+    a.n = lp->n;
+    return launch_primal_pair(lp, lp->tval32T, lp->y32, a, lp->nt ? k_primal32<false, true> : k_primal32<false, false>,
+                              s);
+  }
   if (lp->panels) a.row = lp->rowc;
   if (lp->nt) return launch_step_kernel(k_primal32<false, true>, lp->nbT, s, lp->stream, a);
   return launch_step_kernel(k_primal32<false, false>, lp->nbT, s, lp->stream, a);

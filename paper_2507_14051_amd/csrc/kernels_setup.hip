@@ -292,9 +292,9 @@ __global__ void k_rb_scatter(const int32_t* __restrict__ flags, const int32_t* _
 
 // rbx[4b..4b+3] = {first row, end row, first nonzero, end nonzero} of block b.
 __global__ void k_rb_expand(const int32_t* __restrict__ rb, const int32_t* __restrict__ ptr, int32_t rows,
-                            const int32_t* __restrict__ count, int32_t* __restrict__ rbx) {
+                            const int32_t* __restrict__ count, int64_t cap, int32_t* __restrict__ rbx) {
   int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (b >= rows || b >= *count) return;
+  if (b >= rows || b >= *count || b >= cap) return;  // the host rejects count > cap
   const int s = rb[b], e = rb[b + 1];
   rbx[4 * b] = s;
   rbx[4 * b + 1] = e;
@@ -428,6 +428,77 @@ __global__ void k_pn_remap(const int32_t* __restrict__ row, const int32_t* __res
   const int i = row[q];
   const int l = plid[i], d = dlid[i];
   rowc[q] = plid[i + 1] != l ? m + l : (dlid[i + 1] != d ? m + nL + d : i);
+}
+
+// Columns of A~^T split for the primal side of the dense rows: per column j,
+// the count of its entries from other rows (cntR) and, per slice r of the
+// compact dense index (slices of W), of its entries from dense rows (cntT).
+// Within a column the entries go by increasing row, so by increasing dense
+// index: the slices come in order.  Terminal zeros for the scans.
+__global__ void k_tr_count(const int32_t* __restrict__ cp, const int32_t* __restrict__ row,
+                           const int32_t* __restrict__ dlid, int32_t n, int32_t PT, int32_t W,
+                           int32_t* __restrict__ cntR, int32_t* __restrict__ cntT) {
+  int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j > n) return;
+  if (j == n) {
+    cntR[n] = 0;
+    cntT[(int64_t)PT * n] = 0;
+    return;
+  }
+  for (int r = 0; r < PT; ++r) cntT[(int64_t)r * n + j] = 0;
+  int cr = 0, cur = -1, cc = 0;
+  for (int q = cp[j]; q < cp[j + 1]; ++q) {
+    const int i = row[q];
+    const int d = dlid[i];
+    if (dlid[i + 1] != d) {
+      const int r = d / W;
+      if (r != cur) {
+        if (cur >= 0) cntT[(int64_t)cur * n + j] = cc;
+        cur = r;
+        cc = 0;
+      }
+      ++cc;
+    } else {
+      ++cr;
+    }
+  }
+  if (cur >= 0) cntT[(int64_t)cur * n + j] = cc;
+  cntR[j] = cr;
+}
+
+// The copies: ATR keeps the other rows' entries in order (long rows pointing
+// to their compact y entry m + l), ATD the dense rows' entries by slice, each
+// with its compact dense index d.
+__global__ void k_tr_copy(const int32_t* __restrict__ cp, const int32_t* __restrict__ row,
+                          const double* __restrict__ tval, const float* __restrict__ tval32,
+                          const int32_t* __restrict__ dlid, const int32_t* __restrict__ plid, int32_t n, int32_t m,
+                          int32_t W, const int32_t* __restrict__ cpR, const int32_t* __restrict__ ppT,
+                          int32_t* __restrict__ rowR, double* __restrict__ tvalR, float* __restrict__ tval32R,
+                          int32_t* __restrict__ rowT, double* __restrict__ tvalT, float* __restrict__ tval32T) {
+  int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n) return;
+  int pr = cpR[j], cur = -1, pt = 0;
+  for (int q = cp[j]; q < cp[j + 1]; ++q) {
+    const int i = row[q];
+    const int d = dlid[i];
+    if (dlid[i + 1] != d) {
+      const int r = d / W;
+      if (r != cur) {
+        cur = r;
+        pt = ppT[(int64_t)r * n + j];
+      }
+      rowT[pt] = d;
+      tvalT[pt] = tval[q];
+      if (tval32) tval32T[pt] = tval32[q];
+      ++pt;
+    } else {
+      const int l = plid[i];
+      rowR[pr] = plid[i + 1] != l ? m + l : i;
+      tvalR[pr] = tval[q];
+      if (tval32) tval32R[pr] = tval32[q];
+      ++pr;
+    }
+  }
 }
 
 // First block of each panel (panels start blocks: see k_rb_flags).
@@ -748,7 +819,7 @@ hipError_t launch_transpose(hlp_lp* lp) {
 }
 
 hipError_t launch_build_row_blocks(hlp_lp* lp, const int32_t* ptr, int32_t rows, int32_t* rb, int32_t* rbx,
-                                   int32_t* count, int32_t period) {
+                                   int32_t* count, int32_t period, int64_t rbx_cap) {
   if (rows == 0) return hipSuccess;
   if (rows > lp->rbtmp_rows) return hipErrorInvalidValue;
   hipStream_t s = lp->stream;
@@ -760,7 +831,7 @@ hipError_t launch_build_row_blocks(hlp_lp* lp, const int32_t* ptr, int32_t rows,
   if ((e = scan_exclusive(flags, pos, rows, lp->scan_tmp, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_rb_scatter, dim3(nblocks(rows)), dim3(kBlock), 0, s, flags, pos, rows, rb, count);
   hipLaunchKernelGGL(k_rb_expand, dim3(nblocks(rows)), dim3(kBlock), 0, s, rb, ptr, rows, (const int32_t*)count,
-                     rbx);
+                     rbx_cap < 0 ? (int64_t)rows : rbx_cap, rbx);
   return hipGetLastError();
 }
 
@@ -824,10 +895,31 @@ hipError_t launch_panel_layout(hlp_lp* lp, int32_t* counts) {
                         lp->pval32D)) != hipSuccess)
       return e;
     const int64_t RD = (int64_t)lp->dense_P * nD;
-    if ((e = launch_build_row_blocks(lp, lp->ppD, (int32_t)RD, lp->rbD, lp->rbxD, counts + 5, nD)) != hipSuccess)
+    if ((e = launch_build_row_blocks(lp, lp->ppD, (int32_t)RD, lp->rbD, lp->rbxD, counts + 5, nD,
+                                     lp->capD_blocks)) != hipSuccess)
       return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_dense_transpose(hlp_lp* lp, int32_t* counts) {
+  hipStream_t s = lp->stream;
+  const int32_t n = lp->n, PT = lp->dense_PT;
+  const int64_t RT = (int64_t)PT * n;
+  if (lp->nD < 1 || PT < 1 || PT > lp->dense_PT_cap || RT + 1 > lp->rbtmp_rows + 1) return hipErrorInvalidValue;
+  const float* t32 = lp->precision == HLP_MIXED ? lp->tval32 : nullptr;
+  hipLaunchKernelGGL(k_tr_count, dim3(nblocks((int64_t)n + 1)), dim3(kBlock), 0, s, lp->cp, lp->row, lp->dlid, n,
+                     PT, lp->dense_w, lp->pscrB, lp->pscrA);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = scan_exclusive(lp->pscrB, lp->cpR, (int64_t)n + 1, lp->scan_tmp, s)) != hipSuccess) return e;
+  if ((e = scan_exclusive(lp->pscrA, lp->ppT, RT + 1, lp->scan_tmp, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tr_copy, dim3(nblocks(n)), dim3(kBlock), 0, s, lp->cp, lp->row, lp->tval, t32, lp->dlid,
+                     lp->plid, n, lp->m, lp->dense_w, lp->cpR, lp->ppT, lp->rowR, lp->tvalR,
+                     t32 ? lp->tval32R : nullptr, lp->rowT, lp->tvalT, t32 ? lp->tval32T : nullptr);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_build_row_blocks(lp, lp->cpR, n, lp->rbR, lp->rbxR, counts + 6)) != hipSuccess) return e;
+  return launch_build_row_blocks(lp, lp->ppT, (int32_t)RT, lp->rbT2, lp->rbxT2, counts + 7, n, lp->capT_blocks);
 }
 
 hipError_t launch_panel_remap(hlp_lp* lp) {

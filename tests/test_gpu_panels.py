@@ -240,3 +240,25 @@ def test_panels_leave_adjoint_and_later_solves_unchanged():
     for k in KEYS:
         assert np.array_equal(ga[k], gb[k]), k
     assert np.array_equal(before["x"], after["x"]) and np.array_equal(before["y"], after["y"])
+
+
+def test_panels_and_dense_rows_on_c3a_full_size():
+    """The largest LP (m=2e6, n=5e6, 692M nonzeros, 7,007 rows at the
+    50,000 cap): wide panels, narrow LDS-staged panels on both half-steps and
+    int32 offsets near 7e8; 130 iterations (two runs, a check) agree with the
+    unsplit path."""
+    lp = lpgen.config("c3a", seed=1)
+    announce(f"panels c3a nnz={lp.nnz}")
+    lens = np.diff(lp.A.indptr)
+    a = problem(lp)
+    P, nl = a.panels()
+    PD, nd = a.dense()
+    assert P == 24 and nd == int((lens >= 4096).sum()) and nl == int(((lens > 16) & (lens < 4096)).sum())
+    _, _, eta, _ = a.scaling()
+    oa = np_out(a.solve(tol=0.0, max_iter=130))
+    a.close()
+    b = problem(lp, eta=eta, column_panels=0)
+    ob = np_out(b.solve(tol=0.0, max_iter=130))
+    b.close()
+    print(f"c3a panels vs unsplit: x {rel(oa['x'], ob['x']):.1e} y {rel(oa['y'], ob['y']):.1e}")
+    assert rel(oa["x"], ob["x"]) <= 1e-10 and rel(oa["y"], ob["y"]) <= 1e-10
