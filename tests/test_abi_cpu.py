@@ -90,3 +90,31 @@ def test_graft_build_compiles(tmp_path):
     g.build()
     from paper_2507_14051_amd import hlp
     assert os.path.getsize(hlp.LIB_PATH) > 0
+
+
+def test_panel_parameters_and_workspace():
+    """Column panels are reserved only for large n (or when asked), dense rows
+    only with them; bad panel parameters are rejected before any device work."""
+    import ctypes as C
+    from paper_2507_14051_amd import HlpError, hlp_params_default, hlp_workspace_bytes
+    from paper_2507_14051_amd import hlp as H
+    m, n, nnz = 2_000_000, 5_000_000, 30_000_000
+    base = hlp_workspace_bytes(m, n, nnz, hlp_params_default(column_panels=0))
+    auto = hlp_workspace_bytes(m, n, nnz, hlp_params_default())
+    nodense = hlp_workspace_bytes(m, n, nnz, hlp_params_default(dense_row_min=0))
+    assert base < nodense < auto
+    small = dict(m=1000, n=2000, nnz=5000)
+    assert (hlp_workspace_bytes(*small.values(), hlp_params_default())
+            == hlp_workspace_bytes(*small.values(), hlp_params_default(column_panels=0)))
+    assert (hlp_workspace_bytes(*small.values(), hlp_params_default(column_panels=8))
+            > hlp_workspace_bytes(*small.values(), hlp_params_default(column_panels=0)))
+    # invalid parameters: hlp_lp_create returns HLP_EINVAL before touching the pointers
+    L = H.lib()
+    fake = C.c_void_p(1 << 20)        # never dereferenced: validation fails first
+    out = C.c_void_p()
+    for bad in (dict(column_panels=-2), dict(panel_row_min=0), dict(panel_row_min=16, dense_row_min=16)):
+        p = hlp_params_default(**bad)
+        rc = L.hlp_lp_create(10, 10, 10, fake, fake, fake, fake, fake, fake, fake, fake, C.byref(p), fake,
+                             C.c_size_t(1 << 30), None, C.byref(out))
+        assert rc == -1, bad
+        assert b"panel" in L.hlp_last_error()
