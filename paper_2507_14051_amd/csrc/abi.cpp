@@ -162,8 +162,9 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
   L->rbtmp = c.take<int32_t>(2 * (RB + 1));
   L->rbtmp_rows = RB;
   L->step = c.take<StepDev>(1);
-  // reductions: 4 regions of partial_blocks x 8 doubles (at most one block per row)
-  L->partial_blocks = N + 2;
+  // reductions: 4 regions of partial_blocks x 8 doubles (at most one block per
+  // row, plus the long/dense-row blocks of the panel kernels)
+  L->partial_blocks = N + N / 128 + 8;
   L->partials = c.take<double>(4 * L->partial_blocks * 8);
   L->results = c.take<double>(NSLOT * NQ);
   L->fin_scratch = c.take<double>(4 * 256 * 8);
@@ -181,6 +182,7 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
   L->scan_tmp_len = std::max<int64_t>(L->hist_len, RB + 1) / 1024 + 2;
   L->scan_tmp = c.take<int32_t>(L->scan_tmp_len);
   if (panels > 0) {
+    L->rsum = c.take<double>(3 * nLmax);
     L->lrow = c.take<int32_t>(nLmax);
     L->plid = c.take<int32_t>((int64_t)m + 1);
     L->lbits = c.take<uint32_t>(((int64_t)m + 31) / 32);

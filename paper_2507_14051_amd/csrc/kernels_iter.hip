@@ -335,6 +335,79 @@ __global__ __launch_bounds__(kBlock) void k_dual_pn(DualPanelArgs p) {
   }
 }
 
+// Check iterations with panels: the long and dense rows' sums of one product
+// (out[l] for long row l, out[nL + d] for dense row d), from the partials of
+// the panel kernels, in the same order as k_dual_pn.
+__global__ __launch_bounds__(kBlock) void k_pn_rowsums(const double* __restrict__ part,
+                                                      const double* __restrict__ part2, int32_t P, int32_t nL,
+                                                      int32_t nD, int32_t G, double* __restrict__ out) {
+  const int l = blockIdx.x * kBlock + threadIdx.x;
+  if (l < nL) out[l] = panel_sum(part, P, nL, l);
+  else if (l < nL + nD) out[l] = group_sum(part2, G, nD, l - nL);
+}
+
+// The check-iteration dual half-step with panels: h = A~ xbar, A~ dx and
+// A~ xh from AS for the short rows and from the row sums for the others, the
+// update of k_dual (xhat, the restart and KKT partials), and the compact copy.
+struct DualResArgs {
+  const int4* rb; const int32_t* sp; const int32_t* scol; const double* sval;
+  const double* xbar; const double* dx; const double* xh;
+  double* y; const double* ya; const double* lc; const double* uc; const double* dr;
+  double* yh; double* partials; const StepDev* step;
+  const uint32_t* lbits; const int32_t* lrow; const double* rsum;
+  int32_t nbS, j, m, nL, nD;
+};
+
+__global__ __launch_bounds__(kBlock) void k_dual_pn_res(DualResArgs p) {
+  __shared__ double lds[kRbLds];
+  int i = 0, l = -1;
+  bool own = false;
+  double h = 0.0, adx = 0.0, axh = 0.0, yi = 0.0, lo = 0.0, hi = 0.0, yai = 0.0, dri = 1.0;
+  if ((int)blockIdx.x < p.nbS) {
+    const int4 blk = p.rb[blockIdx.x];
+    i = blk.x + threadIdx.x;
+    const bool in = i < blk.y;
+    int a0 = 0, a1 = 0;
+    if (in) {
+      a0 = p.sp[i]; a1 = p.sp[i + 1];
+      own = !is_long(p.lbits, i);
+      if (own) { yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i]; dri = p.dr[i]; }
+    }
+    const int nr = blk.y - blk.x;
+    h = rb_dot<double>(p.scol, p.sval, p.xbar, blk.z, blk.w, a0, a1, in, nr, lds);
+    adx = rb_dot<double>(p.scol, p.sval, p.dx, blk.z, blk.w, a0, a1, in, nr, lds);
+    axh = rb_dot<double>(p.scol, p.sval, p.xh, blk.z, blk.w, a0, a1, in, nr, lds);
+  } else {
+    l = ((int)blockIdx.x - p.nbS) * kBlock + threadIdx.x;
+    const int nc = p.nL + p.nD;
+    own = l < nc;
+    if (own) {
+      i = p.lrow[l];
+      yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i]; dri = p.dr[i];
+      h = p.rsum[l]; adx = p.rsum[nc + l]; axh = p.rsum[2 * nc + l];
+    }
+  }
+  double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (own) {
+    const double sigma = p.step->sigma, gam = p.step->gamma, a = halpern_a(p.step, p.j);
+    const double w = h - yi / sigma;
+    const double yh = sigma * (clampv(w, lo, hi) - w);
+    const double yn = a * ((1.0 + gam) * yh - gam * yi) + (1.0 - a) * yai;
+    p.y[i] = yn;
+    if (l >= 0) p.y[p.m + l] = yn;
+    p.yh[i] = yh;
+    const double dy = yi - yh;
+    q[0] = dy * dy;
+    q[1] = dy * adx;
+    const double e2 = yh - yai;
+    q[2] = e2 * e2;
+    const double pr = (axh - clampv(axh, lo, hi)) / dri;
+    q[3] = pr * pr;
+    q[4] = (finite(lo) ? lo * fmax(yh, 0.0) : 0.0) - (finite(hi) ? hi * fmax(-yh, 0.0) : 0.0);
+  }
+  block_reduce_store<5>(q, p.partials + (int64_t)blockIdx.x * kRegionStride);
+}
+
 struct Dual32PanelArgs {
   const int4* rb; const int32_t* sp; const int32_t* scol; const float* sval; const float* xbar;
   float* y; const float* ya; const float* lc; const float* uc; const float* b; const StepDev* step;
@@ -803,6 +876,43 @@ hipError_t launch_primal_pair(hlp_lp* lp, const T* tvalT, const T* y, const A& a
   return launch_step_kernel(kprimal, lp->nbR, last, lp->stream, a);
 }
 
+// The panel pipeline of one product A~ v for the long and dense rows, into
+// out[0, nL + nD) (no events).
+hipError_t panel_rowsums(hlp_lp* lp, const double* v, double* out) {
+  hipError_t e;
+  const int32_t G = (lp->dense_P + kDenseGroup - 1) / kDenseGroup;
+  if (lp->nD > 0) {
+    DenseDotArgs<double> da{reinterpret_cast<const int4*>(lp->tilesD), reinterpret_cast<const int4*>(lp->rbxD),
+                            lp->ppD, lp->pcolD, lp->pvalD, v, lp->partD, lp->n};
+    hipLaunchKernelGGL((k_dense_dot<double, false>), dim3(lp->ntilesD), dim3(kBlock), 0, lp->stream, da);
+    hipLaunchKernelGGL(k_dense_combine<double>, dim3(lp->nbCD, G), dim3(kBlock), 0, lp->stream,
+                       (const double*)lp->partD, lp->nD, lp->dense_P, lp->part2D);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (lp->nL > 0) {
+    PanelDotArgs<double> pa{reinterpret_cast<const int4*>(lp->tabP), lp->pp, lp->pcol, lp->pval, v, lp->ppart, {}};
+    for (int k = 0; k < 9; ++k) pa.off[k] = lp->poff[k];
+    hipLaunchKernelGGL((k_panel_dot<double, false>), dim3(lp->nbPgrid), dim3(kBlock), 0, lp->stream, pa);
+  }
+  hipLaunchKernelGGL(k_pn_rowsums, dim3(nblocks((int64_t)lp->nL + lp->nD)), dim3(kBlock), 0, lp->stream,
+                     (const double*)lp->ppart, (const double*)lp->part2D, lp->panels, lp->nL, lp->nD, G, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dual_res_panels(hlp_lp* lp, const StepArgs& s) {
+  const int64_t nc = (int64_t)lp->nL + lp->nD;
+  hipError_t e;
+  if ((e = panel_rowsums(lp, lp->xbar, lp->rsum)) != hipSuccess) return e;
+  if ((e = panel_rowsums(lp, lp->dxv, lp->rsum + nc)) != hipSuccess) return e;
+  if ((e = panel_rowsums(lp, lp->xh, lp->rsum + 2 * nc)) != hipSuccess) return e;
+  DualResArgs d{reinterpret_cast<const int4*>(lp->rbxS), lp->sp, lp->scol, lp->sval, lp->xbar, lp->dxv, lp->xh,
+                lp->y, lp->ya, lp->lct, lp->uct, lp->dr, lp->yh, region(lp, R_DUAL), lp->step, lp->lbits, lp->lrow,
+                lp->rsum, lp->nbS, s.j, lp->m, lp->nL, lp->nD};
+  const int32_t nb = lp->nbS + (int32_t)((nc + kBlock - 1) / kBlock);
+  lp->nb_dual_region = nb;
+  return launch_step_kernel(k_dual_pn_res, nb, s, lp->stream, d);
+}
+
 template <typename T>
 hipError_t refresh_long_y(hlp_lp* lp, T* y) {
   const int32_t nc = lp->nL + lp->nD;  // long rows, then dense rows
@@ -845,7 +955,9 @@ hipError_t launch_dual(hlp_lp* lp, const StepArgs& s) {
   if (lp->nbA == 0) return hipSuccess;
   DualArgs a{reinterpret_cast<const int4*>(lp->rbxA), lp->rp, lp->col, lp->val, lp->xbar, lp->dxv, lp->xh, lp->y, lp->ya, lp->lct, lp->uct,
              lp->dr, lp->yh, region(lp, R_DUAL), s.mask_y, lp->step, s.j};
+  if (s.residual && !s.mask_y && lp->panels) return launch_dual_res_panels(lp, s);
   if (s.mask_y || s.residual) {
+    lp->nb_dual_region = lp->nbA;
     hipError_t e = s.mask_y ? launch_step_kernel(k_dual<2, false>, lp->nbA, s, lp->stream, a)
                             : launch_step_kernel(k_dual<1, false>, lp->nbA, s, lp->stream, a);
     return e != hipSuccess ? e : refresh_long_y(lp, lp->y);
@@ -886,7 +998,7 @@ hipError_t launch_finalize(hlp_lp* lp, int32_t which, int32_t slot) {
   a.dst = lp->results + (int64_t)slot * NQ;
   int nr = 0;
   const bool f32 = (which & 16) != 0;
-  const int64_t nbp = lp->nbT, nbd = lp->nbA;
+  const int64_t nbp = lp->nbT, nbd = lp->nb_dual_region > 0 ? lp->nb_dual_region : lp->nbA;
   if (which & 1) a.r[nr++] = make_region(region(lp, R_PRIMAL), nbp, {Q_DX2, Q_XA2}, 0u);
   if (which & 2) {
     if (f32) a.r[nr++] = make_region(region(lp, R_DUAL), nbd, {Q_DY2, Q_DYADX, Q_YA2}, 0u);
@@ -897,7 +1009,7 @@ hipError_t launch_finalize(hlp_lp* lp, int32_t which, int32_t slot) {
       a.r[nr++] = make_region(region(lp, R_KKT), nbp, {Q_RD2, Q_DOBJ_C, Q_POBJ, Q_VD, Q_VX}, 8u | 16u);
     else a.r[nr++] = make_region(region(lp, R_KKT), nbp, {Q_RD2, Q_DOBJ_C, Q_POBJ}, 0u);
   }
-  if (which & 8) a.r[nr++] = make_region(region(lp, R_ROWS), nbd, {Q_RP2, Q_DOBJ_R, Q_VP}, 4u);
+  if (which & 8) a.r[nr++] = make_region(region(lp, R_ROWS), lp->nbA, {Q_RP2, Q_DOBJ_R, Q_VP}, 4u);
   if (nr == 0) return hipSuccess;
   int64_t nbmax = 0;
   for (int r = 0; r < nr; ++r) nbmax = std::max(nbmax, a.r[r].nb);
@@ -988,6 +1100,7 @@ hipError_t launch_dual32(hlp_lp* lp, const StepArgs& s) {
   Dual32Args a{reinterpret_cast<const int4*>(lp->rbxA), lp->rp, lp->col, lp->val32, lp->xbar32, lp->dx32, lp->y32, lp->ya32, lp->lc32, lp->uc32,
                lp->b32, lp->yh32, region(lp, R_DUAL), lp->step, s.j};
   if (s.residual) {
+    lp->nb_dual_region = lp->nbA;
     hipError_t e = launch_step_kernel(k_dual32<true, false>, lp->nbA, s, lp->stream, a);
     return e != hipSuccess ? e : refresh_long_y(lp, lp->y32);
   }
