@@ -134,6 +134,54 @@ def measure_hbm(dev, name="c3b", iters=640):
     return hbm
 
 
+def measure_adjoint(dev, K=2000, ckpt=100, reps=3):
+    """The differentiation workload (c5: m=50,000, n=100,000, 8 nnz/row): K
+    unrolled iterations with a checkpoint every ckpt (hlp_unrolled_forward),
+    then the reverse pass (hlp_unrolled_backward) for the loss
+    ||x - x_target||^2 + c^T x; times of both and their ratio."""
+    import torch
+
+    import lpgen
+    from paper_2507_14051_amd import Problem
+    from paper_2507_14051_amd.hlp import hlp_tape_bytes, hlp_unrolled_backward, hlp_unrolled_forward
+
+    lp = lpgen.config("c5", seed=1)
+    prob = Problem(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, device=dev)
+    f64 = dict(dtype=torch.float64, device=dev)
+    p = prob.params_for()
+    tape = torch.empty(hlp_tape_bytes(prob.handle, K, ckpt), dtype=torch.uint8, device=dev)
+    x = torch.empty(prob.n, **f64)
+    y = torch.empty(prob.m, **f64)
+    c = torch.as_tensor(lp.c, **f64)
+    xt = torch.as_tensor(lpgen.x_target(lp.n, seed=1), **f64)
+    g = [torch.empty(k, **f64) for k in (prob.n, prob.m, prob.m, prob.n, prob.n)]
+    fw, bw = [], []
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hlp_unrolled_forward(prob.handle, p, K, ckpt, 0, None, None, x, y, tape)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gx = 2.0 * (x - xt) + c
+        gy = torch.zeros_like(y)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        hlp_unrolled_backward(prob.handle, tape, gx, gy, *g)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        if r:
+            fw.append(t1 - t0)
+            bw.append(t3 - t2)
+    prob.close()
+    f, b = min(fw), min(bw)
+    out = {"workload": f"c5: m={lp.m} n={lp.n} nnz={lp.nnz}, K={K} unrolled iterations, checkpoint every {ckpt}",
+           "forward_ms": round(f * 1e3, 2), "backward_ms": round(b * 1e3, 2),
+           "backward_over_forward": round(b / f, 2), "forward_iter_us": round(f / K * 1e6, 2),
+           "tape_mb": round(tape.numel() / 1e6, 1)}
+    log(f"# adjoint: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,6 +294,8 @@ def main():
         hbm = measure_hbm(dev, "c3b", 640)
         hbm_a = measure_hbm(dev, "c3a", 128)
 
+    adjoint = measure_adjoint(dev)
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -268,7 +318,8 @@ def main():
         "time_to_tol_s": round(elapsed / args.steps, 4), "iters_per_solve": infos[-1]["iters"],
         "restarts": infos[-1]["restarts"], "rel_kkt": infos[-1]["rel_kkt"], "all_optimal": ok,
         "setup_s": round(setup_wall, 4), "power_iters": power_iters,
-        "mixed": mixed, "hbm_bound": hbm, "hbm_bound_c3a": hbm_a, "roofline": roofline, "cpu_baseline": cpu,
+        "mixed": mixed, "hbm_bound": hbm, "hbm_bound_c3a": hbm_a, "adjoint": adjoint, "roofline": roofline,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

@@ -263,7 +263,6 @@ hipError_t launch_dual32(hlp_lp* lp, const StepArgs& s);
 hipError_t launch_combine(hlp_lp* lp);  // xh <- xcen + xh32/P, yh <- ycen + yh32/D (P, D from the step)
 hipError_t launch_kkt_rows(hlp_lp* lp);                      // A~ xh (FP64) and row KKT terms
 hipError_t launch_recentre(hlp_lp* lp, double P, double D);  // rebuild the correction data
-hipError_t launch_zero_mixed(hlp_lp* lp);
 hipError_t launch_trace32(hlp_lp* lp, double* dst);
 
 // Adjoint (kernels_adjoint.hip).  Reverse mode of one iteration; mode of the
