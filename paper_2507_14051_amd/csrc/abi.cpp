@@ -238,7 +238,7 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
   // power iteration vectors alias iteration buffers (setup only)
   L->pv = L->rbuf;
   L->pw = L->atyc;
-  L->pu = L->axc;
+  L->pu = panels > 0 ? L->y : L->axc;  // with panels: room for the compact copy
   return c.off;
 }
 

@@ -216,6 +216,8 @@ hipError_t launch_rescale(hlp_lp* lp, int32_t ruiz_iters, int32_t pock_chambolle
 hipError_t launch_scale_vectors(hlp_lp* lp, const double* c, const double* lc, const double* uc,
                                 const double* lv, const double* uv);
 hipError_t launch_power(hlp_lp* lp, int32_t passes, int32_t first_pass, int32_t max_iter, double tol);
+// One power pass with the panel layout (kernels_iter.hip); *nb: partial blocks written.
+hipError_t launch_power_pass_panels(hlp_lp* lp, int64_t* nb);
 hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t s);
 hipError_t launch_fill32(float* p, float v, int64_t n, hipStream_t s);
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);

@@ -408,6 +408,57 @@ __global__ __launch_bounds__(kBlock) void k_dual_pn_res(DualResArgs p) {
   block_reduce_store<5>(q, p.partials + (int64_t)blockIdx.x * kRegionStride);
 }
 
+// Power iteration with panels (setup): w = A~ v from AS for the short rows
+// and from the panel row sums for the long and dense rows, with its compact
+// copy w[m + l]; then u = A~^T w and the block partial sums of u_j^2.
+__global__ __launch_bounds__(kBlock) void k_pw_rows(const int4* __restrict__ rb, const int32_t* __restrict__ sp,
+                                                   const int32_t* __restrict__ scol, const double* __restrict__ sval,
+                                                   const double* __restrict__ v, const uint32_t* __restrict__ lbits,
+                                                   const int32_t* __restrict__ lrow, const double* __restrict__ rsum,
+                                                   int32_t nbS, int32_t m, int32_t nc, double* __restrict__ w,
+                                                   const PowerState* __restrict__ ps) {
+  if (ps->done) return;
+  __shared__ double lds[kRbLds];
+  if ((int)blockIdx.x < nbS) {
+    const int4 blk = rb[blockIdx.x];
+    const int i = blk.x + threadIdx.x;
+    const bool in = i < blk.y;
+    int a0 = 0, a1 = 0;
+    if (in) { a0 = sp[i]; a1 = sp[i + 1]; }
+    const double h = rb_dot<double>(scol, sval, v, blk.z, blk.w, a0, a1, in, blk.y - blk.x, lds);
+    if (in && !is_long(lbits, i)) w[i] = h;
+  } else {
+    const int l = ((int)blockIdx.x - nbS) * kBlock + threadIdx.x;
+    if (l < nc) {
+      const double h = rsum[l];
+      w[lrow[l]] = h;
+      w[m + l] = h;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pw_cols(const int4* __restrict__ rb, const int32_t* __restrict__ cp,
+                                                   const int32_t* __restrict__ row, const double* __restrict__ tval,
+                                                   const double* __restrict__ w, const double* __restrict__ partT,
+                                                   int32_t PT, int32_t n, double* __restrict__ u,
+                                                   double* __restrict__ partials, const PowerState* __restrict__ ps) {
+  if (ps->done) return;
+  __shared__ double lds[kRbLds];
+  const int4 blk = rb[blockIdx.x];
+  const int j = blk.x + threadIdx.x;
+  const bool own = j < blk.y;
+  int a0 = 0, a1 = 0;
+  if (own) { a0 = cp[j]; a1 = cp[j + 1]; }
+  double g = rb_dot<double>(row, tval, w, blk.z, blk.w, a0, a1, own, blk.y - blk.x, lds);
+  if (PT > 0 && own) g += slice_sum(partT, PT, n, j);
+  double q[1] = {0.0};
+  if (own) {
+    u[j] = g;
+    q[0] = g * g;
+  }
+  block_reduce_store<1>(q, partials + blockIdx.x);
+}
+
 struct Dual32PanelArgs {
   const int4* rb; const int32_t* sp; const int32_t* scol; const float* sval; const float* xbar;
   float* y; const float* ya; const float* lc; const float* uc; const float* b; const StepDev* step;
@@ -912,6 +963,37 @@ hipError_t launch_dual_res_panels(hlp_lp* lp, const StepArgs& s) {
   lp->nb_dual_region = nb;
   return launch_step_kernel(k_dual_pn_res, nb, s, lp->stream, d);
 }
+
+}  // namespace
+
+// One power pass u = A~^T (A~ v) with the panel layout; block partial sums of
+// u_j^2 into lp->partials, their count into *nb.
+hipError_t launch_power_pass_panels(hlp_lp* lp, int64_t* nb) {
+  const int32_t nc = lp->nL + lp->nD;
+  hipError_t e;
+  if ((e = panel_rowsums(lp, lp->pv, lp->rsum)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pw_rows, dim3(lp->nbS + (nc + kBlock - 1) / kBlock), dim3(kBlock), 0, lp->stream,
+                     reinterpret_cast<const int4*>(lp->rbxS), lp->sp, lp->scol, lp->sval, lp->pv, lp->lbits, lp->lrow,
+                     lp->rsum, lp->nbS, lp->m, nc, lp->pu, (const PowerState*)lp->pstate);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (lp->ntilesT > 0) {
+    DenseDotArgs<double> da{reinterpret_cast<const int4*>(lp->tilesT), reinterpret_cast<const int4*>(lp->rbxT2),
+                            lp->ppT, lp->rowT, lp->tvalT, lp->pu + lp->m + lp->nL, lp->partT, lp->nD};
+    hipLaunchKernelGGL((k_dense_dot<double, false>), dim3(lp->ntilesT), dim3(kBlock), 0, lp->stream, da);
+    hipLaunchKernelGGL(k_pw_cols, dim3(lp->nbR), dim3(kBlock), 0, lp->stream, reinterpret_cast<const int4*>(lp->rbxR),
+                       lp->cpR, lp->rowR, lp->tvalR, (const double*)lp->pu, (const double*)lp->partT, lp->dense_PT,
+                       lp->n, lp->pw, lp->partials, (const PowerState*)lp->pstate);
+    *nb = lp->nbR;
+  } else {
+    hipLaunchKernelGGL(k_pw_cols, dim3(lp->nbT), dim3(kBlock), 0, lp->stream, reinterpret_cast<const int4*>(lp->rbxT),
+                       lp->cp, lp->rowc, lp->tval, (const double*)lp->pu, (const double*)nullptr, 0, lp->n, lp->pw,
+                       lp->partials, (const PowerState*)lp->pstate);
+    *nb = lp->nbT;
+  }
+  return hipGetLastError();
+}
+
+namespace {
 
 template <typename T>
 hipError_t refresh_long_y(hlp_lp* lp, T* y) {

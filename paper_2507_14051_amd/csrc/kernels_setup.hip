@@ -653,6 +653,19 @@ __global__ void k_power_finish(const double* __restrict__ partials, int64_t nb, 
 
 __global__ void k_power_reset(PowerState* ps) { *ps = PowerState{}; }
 
+constexpr int64_t kSumDirect = 4096;  // partial counts up to this: summed by k_power_finish alone
+
+// out[c] = sum of partials[c*chunk, min(nb, (c+1)*chunk)) in order (one block per chunk).
+__global__ void k_sum_chunks(const double* __restrict__ partials, int64_t nb, int64_t chunk, double* __restrict__ out,
+                             const PowerState* __restrict__ ps) {
+  if (ps->done) return;
+  const int64_t b0 = (int64_t)blockIdx.x * chunk, b1 = min(nb, b0 + chunk);
+  double s = 0.0;
+  for (int64_t b = b0 + threadIdx.x; b < b1; b += kBlock) s += partials[b];
+  double q[1] = {s};
+  block_reduce_store<1>(q, out + blockIdx.x);
+}
+
 __global__ void k_power_normalize(const double* __restrict__ w, double* __restrict__ v, int32_t n,
                                   const PowerState* __restrict__ ps) {
   int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -994,14 +1007,27 @@ hipError_t launch_power(hlp_lp* lp, int32_t passes, int32_t first_pass, int32_t 
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_fill(lp->pv, 1.0 / std::sqrt((double)n), n, s)) != hipSuccess) return e;
   }
-  const int64_t nbc = lp->nbT;
   for (int k = 0; k < passes; ++k) {
-    hipLaunchKernelGGL(k_spmv_plain, dim3(lp->nbA), dim3(kBlock), 0, s, lp->rbA, lp->rp, lp->col, lp->val, lp->pv,
-                       lp->pu, (const PowerState*)lp->pstate, (double*)nullptr);
-    hipLaunchKernelGGL(k_spmv_plain, dim3(lp->nbT), dim3(kBlock), 0, s, lp->rbT, lp->cp, lp->row, lp->tval, lp->pu,
-                       lp->pw, (const PowerState*)lp->pstate, lp->partials);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_power_finish, dim3(1), dim3(kBlock), 0, s, lp->partials, nbc, lp->pstate,
+    int64_t nbc = lp->nbT;
+    if (lp->panels) {
+      if ((e = launch_power_pass_panels(lp, &nbc)) != hipSuccess) return e;
+    } else {
+      hipLaunchKernelGGL(k_spmv_plain, dim3(lp->nbA), dim3(kBlock), 0, s, lp->rbA, lp->rp, lp->col, lp->val, lp->pv,
+                         lp->pu, (const PowerState*)lp->pstate, (double*)nullptr);
+      hipLaunchKernelGGL(k_spmv_plain, dim3(lp->nbT), dim3(kBlock), 0, s, lp->rbT, lp->cp, lp->row, lp->tval, lp->pu,
+                         lp->pw, (const PowerState*)lp->pstate, lp->partials);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    const double* sums = lp->partials;
+    if (nbc > kSumDirect) {  // first pass: at most 256 chunk sums, in order
+      const int64_t chunk = std::max<int64_t>(kSumDirect, (nbc + 255) / 256);
+      const int32_t G = (int32_t)((nbc + chunk - 1) / chunk);
+      hipLaunchKernelGGL(k_sum_chunks, dim3(G), dim3(kBlock), 0, s, lp->partials, nbc, chunk, lp->fin_scratch,
+                         (const PowerState*)lp->pstate);
+      sums = lp->fin_scratch;
+      nbc = G;
+    }
+    hipLaunchKernelGGL(k_power_finish, dim3(1), dim3(kBlock), 0, s, sums, nbc, lp->pstate,
                        max_iter, tol);
     hipLaunchKernelGGL(k_power_normalize, dim3(nblocks(n)), dim3(kBlock), 0, s, lp->pw, lp->pv, n,
                        (const PowerState*)lp->pstate);

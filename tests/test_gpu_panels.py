@@ -176,7 +176,8 @@ def test_panels_mixed_precision():
     b = np_out(prob.solve(tol=0.0, max_iter=300, graphs=0))
     prob.close()
     assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["y"], b["y"])
-    plain = problem(lp, precision=MIXED, column_panels=0)
+    _, _, eta, _ = problem(lp, precision=MIXED, column_panels=16, panel_row_min=8, dense_row_min=512).scaling()
+    plain = problem(lp, eta=eta, precision=MIXED, column_panels=0)
     c = np_out(plain.solve(tol=0.0, max_iter=300))
     plain.close()
     print(f"mixed panels vs unsplit after 300: x {rel(a['x'], c['x']):.1e} y {rel(a['y'], c['y']):.1e}")
@@ -200,9 +201,10 @@ def test_panels_automatic_on_large_skewed_lp():
     lens = np.diff(lp.A.indptr)
     assert P == 24 and nl == int(((lens > 16) & (lens < 4096)).sum())
     assert PD == 2442 and nd == int((lens >= 4096).sum()) > 0
+    _, _, eta, _ = a.scaling()
     oa = np_out(a.solve(tol=0.0, max_iter=200))
     a.close()
-    b = problem(lp, column_panels=0)
+    b = problem(lp, eta=eta, column_panels=0)
     ob = np_out(b.solve(tol=0.0, max_iter=200))
     b.close()
     print(f"c3b panels vs unsplit: x {rel(oa['x'], ob['x']):.1e} y {rel(oa['y'], ob['y']):.1e}")
@@ -229,11 +231,12 @@ def test_panels_leave_adjoint_and_later_solves_unchanged():
     gx = rng.standard_normal(lp.n); gy = rng.standard_normal(lp.m)
     pa = problem(lp, column_panels=8, panel_row_min=8, dense_row_min=400)
     assert pa.panels()[0] == 8 and pa.dense()[1] > 0
+    _, _, eta, _ = pa.scaling()
     before = np_out(pa.solve(tol=0.0, max_iter=150))
     xa, ya, ga = _grads(pa, lp, 120, 25, gx, gy, eval_freq=16)
     after = np_out(pa.solve(tol=0.0, max_iter=150))
     pa.close()
-    pb = problem(lp, column_panels=0)
+    pb = problem(lp, eta=eta, column_panels=0)
     xb, yb, gb = _grads(pb, lp, 120, 25, gx, gy, eval_freq=16)
     pb.close()
     assert np.array_equal(xa, xb) and np.array_equal(ya, yb)
@@ -262,3 +265,19 @@ def test_panels_and_dense_rows_on_c3a_full_size():
     b.close()
     print(f"c3a panels vs unsplit: x {rel(oa['x'], ob['x']):.1e} y {rel(oa['y'], ob['y']):.1e}")
     assert rel(oa["x"], ob["x"]) <= 1e-10 and rel(oa["y"], ob["y"]) <= 1e-10
+
+
+def test_power_iteration_with_panels_matches_oracle():
+    """The setup's power iteration through the panel kernels (wide and narrow
+    panels, the split transpose) gives the oracle's norm estimate."""
+    from oracle.pdhg import power_norm, rescale
+    lp = lpgen.gen(3000, 20000, zipf_alpha=1.3, cap=9000, eq_frac=0.3, free_frac=0.2, values="normal", seed=7)
+    announce("power iteration with panels")
+    prob = problem(lp, column_panels=16, panel_row_min=8, dense_row_min=512)
+    assert prob.dense()[1] > 0
+    _, _, eta, pit = prob.scaling()
+    prob.close()
+    At, _, _ = rescale(lp.A, 10, 1)
+    nrm, it = power_norm(At, 5000, 1e-8)
+    assert eta == pytest.approx(0.998 / nrm, rel=1e-9)
+    assert abs(pit - it) <= 1
