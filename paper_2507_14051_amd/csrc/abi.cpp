@@ -208,7 +208,7 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
   }
   if (nDmax > 0) {
     L->ppD = c.take<int32_t>(RD + 1);
-    L->pcolD = c.take<int32_t>(nnz);
+    L->pcolD = c.take<uint16_t>(nnz);
     L->pvalD = c.take<double>(nnz);
     L->pval32D = mixed ? c.take<float>(nnz) : nullptr;
     L->partD = c.take<double>(RD);
@@ -223,7 +223,7 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
     L->tvalR = c.take<double>(nnz);
     L->tval32R = mixed ? c.take<float>(nnz) : nullptr;
     L->ppT = c.take<int32_t>(RT + 1);
-    L->rowT = c.take<int32_t>(nnz);
+    L->rowT = c.take<uint16_t>(nnz);
     L->tvalT = c.take<double>(nnz);
     L->tval32T = mixed ? c.take<float>(nnz) : nullptr;
     L->partT = c.take<double>(RT);

@@ -120,8 +120,8 @@ __device__ __forceinline__ T ld(const T* p) {
 }
 
 // STAGE: write each product to lds[q - first] instead of summing.
-template <int STRIDE, int U, bool STAGE, bool NT, typename ACC, typename V, typename X>
-__device__ __forceinline__ ACC strided_batches(const int32_t* __restrict__ idx, const V* __restrict__ val,
+template <int STRIDE, int U, bool STAGE, bool NT, typename ACC, typename I, typename V, typename X>
+__device__ __forceinline__ ACC strided_batches(const I* __restrict__ idx, const V* __restrict__ val,
                                                const X* __restrict__ vec, int xoff, int first, int end,
                                                int lane, ACC* lds) {
   ACC part = 0;
@@ -133,7 +133,7 @@ __device__ __forceinline__ ACC strided_batches(const int32_t* __restrict__ idx, 
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int q = min(base + u * STRIDE, end - 1);
-      ix[u] = ld<NT>(idx + q);
+      ix[u] = (int)ld<NT>(idx + q);
       vv[u] = ld<NT>(val + q);
     }
     X g[U];
@@ -156,8 +156,8 @@ __device__ __forceinline__ ACC strided_batches(const int32_t* __restrict__ idx, 
 // The batch depth is uniform over the lanes that share [first, end) (a block
 // or a wave).  Either way a lane adds its products in increasing position, so
 // the result does not depend on the depth.
-template <int STRIDE, bool STAGE, bool NT, typename ACC, typename V, typename X>
-__device__ __forceinline__ ACC strided_products(const int32_t* __restrict__ idx, const V* __restrict__ val,
+template <int STRIDE, bool STAGE, bool NT, typename ACC, typename I, typename V, typename X>
+__device__ __forceinline__ ACC strided_products(const I* __restrict__ idx, const V* __restrict__ val,
                                                 const X* __restrict__ vec, int xoff, int first, int end,
                                                 int lane, ACC* lds) {
   const int per_lane = (end - first + STRIDE - 1) / STRIDE;
@@ -168,13 +168,14 @@ __device__ __forceinline__ ACC strided_products(const int32_t* __restrict__ idx,
   return strided_batches<STRIDE, kRbUnroll, STAGE, NT, ACC>(idx, val, vec, xoff, first, end, lane, lds);
 }
 
-// Row sums of val .* vec[idx - xoff] over the calling block's nrows rows with
+// Row sums of val .* vec[idx - xoff] (idx: int32, or uint16 offsets into a
+// staged slice) over the calling block's nrows rows with
 // nonzeros [ps, pe); thread t (own: t < nrows) holds the pointers [a0, a1) of
 // its row and gets that row's sum (in a single-row block every thread gets
 // it).  Deterministic in every kind of block.  (xoff: vec holds the slice of
 // the vector that starts at index xoff, e.g. a slice staged in LDS.)
-template <typename ACC, bool NT = false, typename V, typename X>
-__device__ __forceinline__ ACC rb_dot(const int32_t* __restrict__ idx, const V* __restrict__ val,
+template <typename ACC, bool NT = false, typename I, typename V, typename X>
+__device__ __forceinline__ ACC rb_dot(const I* __restrict__ idx, const V* __restrict__ val,
                                       const X* __restrict__ vec, int ps, int pe, int a0, int a1,
                                       bool own, int nrows, ACC* lds, int xoff = 0) {
   const int tid = threadIdx.x;

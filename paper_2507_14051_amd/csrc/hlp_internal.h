@@ -106,7 +106,8 @@ struct hlp_lp {
   // lrow[nL + d] in narrow panel q.  A tile = consecutive row blocks of one
   // narrow panel, reduced by one block with the panel's slice of xbar in LDS.
   int32_t dense_min = 0, dense_P = 0, dense_w = 0, nD = 0, nD_cap = 0;
-  int32_t *dlid = nullptr, *ppD = nullptr, *pcolD = nullptr;
+  int32_t *dlid = nullptr, *ppD = nullptr;
+  uint16_t* pcolD = nullptr;  // column offset in the narrow panel
   double* pvalD = nullptr;
   float* pval32D = nullptr;
   double* partD = nullptr;   // dense_P * nD partial sums (float in the FP32 path)
@@ -118,7 +119,8 @@ struct hlp_lp {
   // slices of dense_w entries of the compact copy of y (row r*n + j = the
   // entries of column j whose dense index lies in slice r), with its tiles.
   int32_t dense_PT = 0, dense_PT_cap = 0;
-  int32_t *cpR = nullptr, *rowR = nullptr, *ppT = nullptr, *rowT = nullptr;
+  int32_t *cpR = nullptr, *rowR = nullptr, *ppT = nullptr;
+  uint16_t* rowT = nullptr;  // offset of the dense index in its slice
   double *tvalR = nullptr, *tvalT = nullptr;
   float *tval32R = nullptr, *tval32T = nullptr;
   double* partT = nullptr;  // dense_PT * n partial sums (float in the FP32 path)
@@ -187,9 +189,9 @@ hlp_err hip_fail(hipError_t e, const char* what);
 // Carve the workspace.  With lp->... == nullptr base, only computes the size.
 size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t precision, int32_t panels,
              int32_t panel_row_min, int32_t dense_row_min);
-constexpr int32_t kDenseW = 2048;     // columns per narrow panel (its FP64 slice: 16 KB of LDS)
+constexpr int32_t kDenseW = 2048;     // columns per narrow panel (its FP64 slice: 16 KB of LDS; < 65536)
 constexpr int32_t kDenseGroup = 64;   // narrow panels summed per group
-constexpr int32_t kTileBlocks = 16;   // row blocks per tile
+constexpr int32_t kTileBlocks = 32;   // row blocks per tile
 constexpr int32_t kMaxDense = 65536;  // dense rows at most (more: no dense class)
 // Upper bound on the row blocks of a CSR with `rows` rows and nnz nonzeros
 // (see the row-block rules in device.h), with panels of `period` rows.

@@ -220,10 +220,10 @@ __device__ __forceinline__ T panel_sum(const T* __restrict__ part, int32_t P, in
 
 // Dense rows: a tile is up to kTileBlocks row blocks of one narrow panel of
 // AD; the block stages the panel's slice of the vector in LDS once and
-// gathers from there.
+// gathers from there (the indices are 16-bit offsets in the slice).
 template <typename T>
 struct DenseDotArgs {
-  const int4* tiles; const int4* rbx; const int32_t* pp; const int32_t* pcol; const T* pval; const T* vec;
+  const int4* tiles; const int4* rbx; const int32_t* pp; const uint16_t* pcol; const T* pval; const T* vec;
   T* out; int32_t n;
 };
 
@@ -231,18 +231,21 @@ template <typename T, bool NT>
 __global__ __launch_bounds__(kBlock) void k_dense_dot(DenseDotArgs<T> p) {
   __shared__ T xs[kDenseW];
   __shared__ T lds[kRbLds];
+  __shared__ int4 tb[kTileBlocks];
   const int4 tile = p.tiles[blockIdx.x];
   const int c0 = tile.z * kDenseW;
   const int nc = min(kDenseW, p.n - c0);
+  const int nbk = tile.y - tile.x;  // at most kTileBlocks
+  if ((int)threadIdx.x < nbk) tb[threadIdx.x] = p.rbx[tile.x + threadIdx.x];
   for (int c = threadIdx.x; c < nc; c += kBlock) xs[c] = p.vec[c0 + c];
   __syncthreads();
-  for (int b = tile.x; b < tile.y; ++b) {  // uniform over the block
-    const int4 blk = p.rbx[b];
+  for (int b = 0; b < nbk; ++b) {  // uniform over the block
+    const int4 blk = tb[b];
     const int r = blk.x + threadIdx.x;
     const bool own = r < blk.y;
     int a0 = 0, a1 = 0;
     if (own) { a0 = p.pp[r]; a1 = p.pp[r + 1]; }
-    const T acc = rb_dot<T, NT>(p.pcol, p.pval, xs, blk.z, blk.w, a0, a1, own, blk.y - blk.x, lds, c0);
+    const T acc = rb_dot<T, NT>(p.pcol, p.pval, xs, blk.z, blk.w, a0, a1, own, blk.y - blk.x, lds);
     if (own) p.out[r] = acc;
   }
 }

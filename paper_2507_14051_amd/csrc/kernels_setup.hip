@@ -401,18 +401,21 @@ __global__ void k_pn_seg(const int32_t* __restrict__ rp, const int32_t* __restri
 }
 
 // One block per long row: each nonzero to its panel's segment, order kept.
+// I = int32_t stores the column; I = uint16_t its offset in the panel (W <= 65536).
+template <typename I>
 __global__ void k_pn_long(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                           const double* __restrict__ val, const float* __restrict__ val32,
                           const int32_t* __restrict__ lrow, int32_t nL, int32_t W, const int32_t* __restrict__ pp,
-                          const int32_t* __restrict__ seg0, int32_t* __restrict__ pcol, double* __restrict__ pval,
+                          const int32_t* __restrict__ seg0, I* __restrict__ pcol, double* __restrict__ pval,
                           float* __restrict__ pval32) {
   const int l = blockIdx.x;
   const int i = lrow[l];
   for (int q = rp[i] + threadIdx.x; q < rp[i + 1]; q += kBlock) {
     const int j = col[q];
-    const int64_t t = (int64_t)(j / W) * nL + l;
+    const int p = j / W;
+    const int64_t t = (int64_t)p * nL + l;
     const int dst = pp[t] + (q - seg0[t]);
-    pcol[dst] = j;
+    pcol[dst] = sizeof(I) == 4 ? (I)j : (I)(j - p * W);
     pval[dst] = val[q];
     if (val32) pval32[dst] = val32[q];
   }
@@ -468,13 +471,13 @@ __global__ void k_tr_count(const int32_t* __restrict__ cp, const int32_t* __rest
 
 // The copies: ATR keeps the other rows' entries in order (long rows pointing
 // to their compact y entry m + l), ATD the dense rows' entries by slice, each
-// with its compact dense index d.
+// with the offset of its compact dense index d in the slice.
 __global__ void k_tr_copy(const int32_t* __restrict__ cp, const int32_t* __restrict__ row,
                           const double* __restrict__ tval, const float* __restrict__ tval32,
                           const int32_t* __restrict__ dlid, const int32_t* __restrict__ plid, int32_t n, int32_t m,
                           int32_t W, const int32_t* __restrict__ cpR, const int32_t* __restrict__ ppT,
                           int32_t* __restrict__ rowR, double* __restrict__ tvalR, float* __restrict__ tval32R,
-                          int32_t* __restrict__ rowT, double* __restrict__ tvalT, float* __restrict__ tval32T) {
+                          uint16_t* __restrict__ rowT, double* __restrict__ tvalT, float* __restrict__ tval32T) {
   int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (j >= n) return;
   int pr = cpR[j], cur = -1, pt = 0;
@@ -487,7 +490,7 @@ __global__ void k_tr_copy(const int32_t* __restrict__ cp, const int32_t* __restr
         cur = r;
         pt = ppT[(int64_t)r * n + j];
       }
-      rowT[pt] = d;
+      rowT[pt] = (uint16_t)(d - r * W);  // offset in the slice
       tvalT[pt] = tval[q];
       if (tval32) tval32T[pt] = tval32[q];
       ++pt;
@@ -865,8 +868,9 @@ hipError_t launch_panel_split(hlp_lp* lp, int32_t T, int32_t Ld, int32_t* counts
 namespace {
 // Panel-major copy of the rows lrow[0, nrows): segment t = p*nrows + l, its
 // row pointers pp (via the scratch arrays), then the nonzeros.
+template <typename I>
 hipError_t panel_copy(hlp_lp* lp, const int32_t* rows, int32_t nrows, int32_t P, int32_t W, int32_t* pp,
-                      int32_t* pcol, double* pval, float* pval32) {
+                      I* pcol, double* pval, float* pval32) {
   hipStream_t s = lp->stream;
   const int64_t R = (int64_t)P * nrows;
   if (nrows < 1 || R + 1 > lp->rbtmp_rows + 1) return hipErrorInvalidValue;
@@ -876,7 +880,7 @@ hipError_t panel_copy(hlp_lp* lp, const int32_t* rows, int32_t nrows, int32_t P,
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if ((e = scan_exclusive(lp->pscrA, pp, R + 1, lp->scan_tmp, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pn_long, dim3(nrows), dim3(kBlock), 0, s, lp->rp, lp->col, lp->val, v32, rows, nrows, W,
+  hipLaunchKernelGGL(k_pn_long<I>, dim3(nrows), dim3(kBlock), 0, s, lp->rp, lp->col, lp->val, v32, rows, nrows, W,
                      pp, lp->pscrB, pcol, pval, v32 ? pval32 : nullptr);
   return hipGetLastError();
 }
