@@ -189,6 +189,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation workload")
     ap.add_argument("--no-hbm", action="store_true", help="skip the HBM-bound skewed LPs (c3b, c3a)")
     ap.add_argument("--profile-iters", type=int, default=400)
     ap.add_argument("--kernels-only", action="store_true",
@@ -294,7 +295,7 @@ def main():
         hbm = measure_hbm(dev, "c3b", 640)
         hbm_a = measure_hbm(dev, "c3a", 128)
 
-    adjoint = measure_adjoint(dev)
+    adjoint = None if args.no_adjoint else measure_adjoint(dev)
 
     cpu = None
     if not args.no_cpu:
