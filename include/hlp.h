@@ -117,8 +117,11 @@ typedef struct {
                               this many nonzeros are "dense": their nonzeros are also
                               grouped by narrow panels of 2048 columns, whose slice of
                               xbar a block stages in LDS; the per-panel partial row sums
-                              are added in panel order.  0: no dense rows; otherwise
-                              > panel_row_min; 4096 */
+                              are added in panel order.  When the dense rows hold at
+                              least half of the nonzeros, their entries of A~^T are
+                              split off the same way for the primal half-step.  At
+                              most 65,536 dense rows (with more, the rows stay long).
+                              0: no dense rows; otherwise > panel_row_min; 4096 */
 } hlp_params;
 
 /* Outcome of a solve.  Objectives and relative errors refer to the original
