@@ -281,3 +281,21 @@ def test_power_iteration_with_panels_matches_oracle():
     nrm, it = power_norm(At, 5000, 1e-8)
     assert eta == pytest.approx(0.998 / nrm, rel=1e-9)
     assert abs(pit - it) <= 1
+
+
+def test_more_dense_rows_than_reserved_stay_long():
+    """With dense_row_min = 20 the c3b LP has about 100,000 rows above it, more
+    than the 65,536 dense rows the workspace holds: they stay long rows."""
+    lp = lpgen.config("c3b", seed=1)
+    lens = np.diff(lp.A.indptr)
+    assert (lens >= 20).sum() > 65536
+    announce("panels dense overflow (c3b)")
+    a = problem(lp, dense_row_min=20)
+    assert a.dense() == (0, 0) and a.panels() == (24, int((lens > 16).sum()))
+    _, _, eta, _ = a.scaling()
+    oa = np_out(a.solve(tol=0.0, max_iter=70))
+    a.close()
+    b = problem(lp, eta=eta, column_panels=0)
+    ob = np_out(b.solve(tol=0.0, max_iter=70))
+    b.close()
+    assert rel(oa["x"], ob["x"]) <= 1e-10 and rel(oa["y"], ob["y"]) <= 1e-10
