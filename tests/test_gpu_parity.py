@@ -266,3 +266,26 @@ def test_graph_replay_c2_partial_run():
     assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["y"], b["y"])
     assert a["info"]["iters"] == b["info"]["iters"] == 3000
     prob.close()
+
+
+@pytest.mark.timeout(600)
+def test_c3b_full_size_first_iterations_match_oracle():
+    """The large skewed LP at its full size (m=2e6, n=5e6, 29.6M nonzeros) in
+    the bench's configuration (column panels, dense rows): scaling diagonals
+    and the end point after 3 iterations (a check, a plain iteration, a check)
+    against the oracle.  Both sides take the same given stepsize, so the
+    oracle's power iteration (minutes at this size) is not needed."""
+    lp = lpgen.config("c3b", seed=1)
+    announce(f"c3b full size vs oracle nnz={lp.nnz}")
+    eta = 1e-3
+    prob = problem(lp, eta=eta)
+    assert prob.panels()[0] == 24 and prob.dense()[1] > 0
+    dr, dc, _, _ = prob.scaling()
+    out = np_out(prob.solve(tol=0.0, max_iter=3))
+    prob.close()
+    At, dr0, dc0 = rescale(lp.A, 10, 1)
+    assert rel(dr.cpu().numpy(), dr0) <= 1e-12 and rel(dc.cpu().numpy(), dc0) <= 1e-12
+    ref = oracle.solve(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, Params(tol=0.0, max_iter=3, eta_override=eta))
+    ex, ey = rel(out["x"], ref.x), rel(out["y"], ref.y)
+    print(f"c3b 3 iterations vs oracle: x {ex:.1e} y {ey:.1e}")
+    assert ex <= TRAJ_TOL and ey <= TRAJ_TOL
