@@ -29,6 +29,7 @@ for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
 import argparse
 import hashlib
 import json
+import math
 import re
 import sys
 import time
@@ -182,6 +183,61 @@ def measure_adjoint(dev, K=2000, ckpt=100, reps=3):
     return out
 
 
+# Switches of the method the paper argues for (Sec. 3).  PID gains (theta, 0, 0)
+# are the exponentially smoothed distance-ratio primal-weight update the paper
+# attributes to cuPDLP, theta = 1 its unsmoothed form; zero gains keep the
+# weight fixed.  A beta of -1 turns a decay test off, 1e18 the artificial one.
+ABLATIONS = {
+    "paper_default": {},
+    "halpern_gamma0": dict(gamma=0.0),
+    "gamma_half": dict(gamma=0.5),
+    "omega_ratio": dict(kp=1.0, ki=0.0, kd=0.0),
+    "omega_smoothed": dict(kp=0.5, ki=0.0, kd=0.0),
+    "omega_fixed": dict(kp=0.0, ki=0.0, kd=0.0),
+    "no_sufficient": dict(beta_sufficient=-1.0),
+    "no_necessary": dict(beta_necessary=-1.0),
+    "no_artificial": dict(beta_artificial=1e18),
+    "no_restarts": dict(beta_sufficient=-1.0, beta_necessary=-1.0, beta_artificial=1e18),
+}
+
+
+def measure_ablation(dev, max_iter=600000, c1_seeds=8):
+    """Iterations to 1e-8 relative KKT under each switch: the medium LP (seed
+    1) and the geometric mean over c1_seeds small LPs, relative to the
+    paper's settings.  One handle per LP, so every variant takes the same
+    scaling and stepsize."""
+    import torch
+
+    import lpgen
+    from paper_2507_14051_amd import Problem
+
+    def run(lp, tag):
+        prob = Problem(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, device=dev)
+        res = {}
+        for name, kw in ABLATIONS.items():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = prob.solve(tol=1e-8, max_iter=max_iter, want_r=False, **kw)["info"]
+            torch.cuda.synchronize()
+            res[name] = {"iters": info["iters"], "restarts": info["restarts"], "status": info["status"],
+                         "rel_kkt": info["rel_kkt"], "time_s": round(time.perf_counter() - t0, 3)}
+            log(f"# ablation {tag} {name}: {res[name]}")
+        prob.close()
+        return res
+
+    med = run(lpgen.config("c2", seed=1), "c2")
+    base = med["paper_default"]["iters"]
+    for r in med.values():
+        r["iters_vs_default"] = round(r["iters"] / base, 3)
+    small = [run(lpgen.config("c1", seed=s), f"c1 seed {s}") for s in range(1, c1_seeds + 1)]
+    geo = {}
+    for name in ABLATIONS:
+        ratios = [r[name]["iters"] / r["paper_default"]["iters"] for r in small]
+        geo[name] = {"geomean_iters_vs_default": round(math.exp(sum(map(math.log, ratios)) / len(ratios)), 3),
+                     "solved": sum(r[name]["status"] == 0 for r in small), "of": len(small)}
+    return {"tol": 1e-8, "max_iter": max_iter, "c2_seed1": med, f"c1_seeds_1_to_{c1_seeds}": geo}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +254,9 @@ def main():
     ap.add_argument("--hbm-only", action="store_true", help="only the skewed-LP measurement (for profiling it)")
     ap.add_argument("--hbm-workload", default="c3b", choices=("c3b", "c3a"),
                     help="LP of --hbm-only (c3a: ~6.9e8 nonzeros, minutes to generate)")
+    ap.add_argument("--ablation", action="store_true",
+                    help="only the iterations-to-tolerance of the method's switches (reflection, primal weight, "
+                         "restart tests)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -209,6 +268,9 @@ def main():
     from paper_2507_14051_amd import MIXED, OPTIMAL, Problem
 
     dev = torch.device("cuda:0")
+    if args.ablation:
+        print(json.dumps({"ablation": measure_ablation(dev)}), flush=True)
+        return
     if args.hbm_only:
         iters = 640 if args.hbm_workload == "c3b" else 128
         print(json.dumps({"hbm_only": True, "hbm_bound": measure_hbm(dev, args.hbm_workload, iters)}), flush=True)

@@ -289,3 +289,42 @@ def test_c3b_full_size_first_iterations_match_oracle():
     ex, ey = rel(out["x"], ref.x), rel(out["y"], ref.y)
     print(f"c3b 3 iterations vs oracle: x {ex:.1e} y {ey:.1e}")
     assert ex <= TRAJ_TOL and ey <= TRAJ_TOL
+
+
+# Switches of the method the paper argues for (Sec. 3): the reflection gamma,
+# the primal-weight rule and each of the three restart conditions.  PID gains
+# (theta, 0, 0) are the exponentially smoothed distance-ratio update the paper
+# attributes to cuPDLP (log w' = theta log(|dy|/|dx|) + (1-theta) log w),
+# theta = 1 its unsmoothed form; zero gains keep w fixed.  A beta of -1 turns
+# off a decay test, beta_artificial = 1e18 the artificial restart.
+ABLATIONS = {
+    "halpern_gamma0": dict(gamma=0.0),
+    "gamma_half": dict(gamma=0.5),
+    "omega_ratio": dict(kp=1.0, ki=0.0, kd=0.0),
+    "omega_smoothed": dict(kp=0.5, ki=0.0, kd=0.0),
+    "omega_fixed": dict(kp=0.0, ki=0.0, kd=0.0),
+    "pid_with_d": dict(kp=0.5, ki=0.25, kd=0.125),
+    "no_sufficient": dict(beta_sufficient=-1.0),
+    "no_necessary": dict(beta_necessary=-1.0),
+    "no_artificial": dict(beta_artificial=1e18),
+    "no_restarts": dict(beta_sufficient=-1.0, beta_necessary=-1.0, beta_artificial=1e18),
+}
+
+
+@pytest.mark.parametrize("name", sorted(ABLATIONS))
+def test_ablation_settings_match_oracle(name):
+    """Each switch runs the same iteration as the oracle: the first 100
+    iterates, the iteration and restart counts, the primal weight, the end
+    point and its KKT error (a run to 1e-8, capped at 20,000 iterations)."""
+    lp = lpgen.config("c1", seed=2)
+    announce(f"ablation {name} c1 seed=2")
+    kw = ABLATIONS[name]
+    out, ref, worst = _trajectory_case(lp, T=100, tol=1e-8, max_iter=20000, **kw)
+    info = out["info"]
+    assert info["status"] == ref.status and info["iters"] == ref.iters and info["restarts"] == ref.restarts
+    assert info["omega"] == pytest.approx(ref.omega, rel=1e-8)
+    assert rel(out["x"].cpu().numpy(), ref.x) <= 1e-8 and rel(out["y"].cpu().numpy(), ref.y) <= 1e-8
+    assert info["rel_kkt"] == pytest.approx(ref.info["rel_kkt"], rel=1e-6)
+    if name == "no_restarts":
+        assert info["restarts"] == 0 and info["omega"] == 1.0
+    print(f"{name}: {info['iters']} iterations, {info['restarts']} restarts, worst trajectory error {worst:.1e}")
