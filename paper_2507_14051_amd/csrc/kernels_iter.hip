@@ -227,8 +227,48 @@ struct DenseDotArgs {
   T* out; int32_t n;
 };
 
+// A block of short rows (the staged kind of rb_dot) holds at most kRbLds
+// nonzeros: kDenseSlots per thread at stride kBlock.
+constexpr int kDenseSlots = (kRbLds + kBlock - 1) / kBlock;
+
+__device__ __forceinline__ bool staged_kind(int4 blk) {
+  const int nrows = blk.y - blk.x;
+  return nrows > 1 && blk.w - blk.z <= nrows * kRbSerial;
+}
+
+// One staged row block's matrix entries and row pointers, loaded ahead of use.
+template <typename T>
+struct DenseRegs {
+  int ix[kDenseSlots];
+  T v[kDenseSlots];
+  int a0, a1;
+};
+
 template <typename T, bool NT>
-__global__ __launch_bounds__(kBlock) void k_dense_dot(DenseDotArgs<T> p) {
+__device__ __forceinline__ void dense_load(const DenseDotArgs<T>& p, int4 blk, DenseRegs<T>& R) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kDenseSlots; ++u) {
+    const int q = blk.z + tid + u * kBlock;
+    R.ix[u] = 0;
+    R.v[u] = T(0);
+    if (q < blk.w) {
+      R.ix[u] = (int)ld<NT>(p.pcol + q);
+      R.v[u] = ld<NT>(p.pval + q);
+    }
+  }
+  const int r = blk.x + tid;
+  R.a0 = R.a1 = 0;
+  if (r < blk.y) { R.a0 = p.pp[r]; R.a1 = p.pp[r + 1]; }
+}
+
+// The row blocks of a tile run one after another; for the staged kind the
+// next block's entries and row pointers are loaded before the current block
+// is reduced, so their latency overlaps the LDS work.  The sums are those of
+// rb_dot: products staged at their position, each row added serially.
+// (Four waves per SIMD is also what the LDS allows for T = double.)
+template <typename T, bool NT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_dense_dot(DenseDotArgs<T> p) {
   __shared__ T xs[kDenseW];
   __shared__ T lds[kRbLds];
   __shared__ int4 tb[kTileBlocks];
@@ -236,17 +276,38 @@ __global__ __launch_bounds__(kBlock) void k_dense_dot(DenseDotArgs<T> p) {
   const int c0 = tile.z * kDenseW;
   const int nc = min(kDenseW, p.n - c0);
   const int nbk = tile.y - tile.x;  // at most kTileBlocks
-  if ((int)threadIdx.x < nbk) tb[threadIdx.x] = p.rbx[tile.x + threadIdx.x];
-  for (int c = threadIdx.x; c < nc; c += kBlock) xs[c] = p.vec[c0 + c];
+  const int tid = threadIdx.x;
+  if (tid < nbk) tb[tid] = p.rbx[tile.x + tid];
+  for (int c = tid; c < nc; c += kBlock) xs[c] = p.vec[c0 + c];
   __syncthreads();
+  DenseRegs<T> cur, nxt;
+  if (nbk > 0 && staged_kind(tb[0])) dense_load<T, NT>(p, tb[0], cur);
   for (int b = 0; b < nbk; ++b) {  // uniform over the block
     const int4 blk = tb[b];
-    const int r = blk.x + threadIdx.x;
+    const int r = blk.x + tid;
     const bool own = r < blk.y;
-    int a0 = 0, a1 = 0;
-    if (own) { a0 = p.pp[r]; a1 = p.pp[r + 1]; }
-    const T acc = rb_dot<T, NT>(p.pcol, p.pval, xs, blk.z, blk.w, a0, a1, own, blk.y - blk.x, lds);
-    if (own) p.out[r] = acc;
+    const bool pre = b + 1 < nbk && staged_kind(tb[b + 1]);
+    if (staged_kind(blk)) {
+      if (pre) dense_load<T, NT>(p, tb[b + 1], nxt);
+#pragma unroll
+      for (int u = 0; u < kDenseSlots; ++u) {
+        const int q = tid + u * kBlock;
+        if (q < blk.w - blk.z) lds[q] = cur.v[u] * xs[cur.ix[u]];
+      }
+      __syncthreads();
+      T acc = T(0);
+      if (own)
+        for (int q = cur.a0 - blk.z; q < cur.a1 - blk.z; ++q) acc += lds[q];
+      __syncthreads();
+      if (own) p.out[r] = acc;
+      if (pre) cur = nxt;
+    } else {
+      int a0 = 0, a1 = 0;
+      if (own) { a0 = p.pp[r]; a1 = p.pp[r + 1]; }
+      const T acc = rb_dot<T, NT>(p.pcol, p.pval, xs, blk.z, blk.w, a0, a1, own, blk.y - blk.x, lds);
+      if (own) p.out[r] = acc;
+      if (pre) dense_load<T, NT>(p, tb[b + 1], cur);
+    }
   }
 }
 
