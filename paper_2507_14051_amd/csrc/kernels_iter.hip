@@ -178,12 +178,95 @@ __global__ void k_refresh_long_y(T* __restrict__ y, const int32_t* __restrict__ 
   if (l < nL) y[m + l] = y[lrow[l]];
 }
 
+// A run of row blocks reduced one after another by one workgroup.  For the
+// staged kind (short rows, at most kRbLds nonzeros) the next block's entries
+// and row pointers are loaded while the current block is reduced, so their
+// latency overlaps the gathers and the LDS work.  The sums are those of
+// rb_dot: products staged at their position, each row added serially.
+constexpr int kStagedSlots = (kRbLds + kBlock - 1) / kBlock;  // per thread, at stride kBlock
+
+__device__ __forceinline__ bool staged_kind(int4 blk) {
+  const int nrows = blk.y - blk.x;
+  return nrows > 1 && blk.w - blk.z <= nrows * kRbSerial;
+}
+
+template <typename T>
+struct StagedRegs {
+  int ix[kStagedSlots];
+  T v[kStagedSlots];
+  int a0, a1;
+};
+
+template <bool NT, typename T, typename I>
+__device__ __forceinline__ void staged_load(const I* __restrict__ idx, const T* __restrict__ val,
+                                            const int32_t* __restrict__ ptr, int4 blk, StagedRegs<T>& R) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kStagedSlots; ++u) {
+    const int q = blk.z + tid + u * kBlock;
+    R.ix[u] = 0;
+    R.v[u] = T(0);
+    if (q < blk.w) {
+      R.ix[u] = (int)ld<NT>(idx + q);
+      R.v[u] = ld<NT>(val + q);
+    }
+  }
+  const int r = blk.x + tid;
+  R.a0 = R.a1 = 0;
+  if (r < blk.y) { R.a0 = ptr[r]; R.a1 = ptr[r + 1]; }
+}
+
+// tb: the nbk row blocks (in LDS); out[r] = row r's sum of val .* vec[idx].
+// cur: the first block's loads if it is of the staged kind (the caller issues
+// them, so they can overlap its own set-up).
+template <typename T, bool NT, typename I>
+__device__ __forceinline__ void row_block_run(const int4* tb, int nbk, const I* __restrict__ idx,
+                                              const T* __restrict__ val, const int32_t* __restrict__ ptr,
+                                              const T* __restrict__ vec, T* __restrict__ out, T* lds,
+                                              StagedRegs<T>& cur) {
+  const int tid = threadIdx.x;
+  StagedRegs<T> nxt;
+  for (int b = 0; b < nbk; ++b) {  // uniform over the workgroup
+    const int4 blk = tb[b];
+    const int r = blk.x + tid;
+    const bool own = r < blk.y;
+    const bool pre = b + 1 < nbk && staged_kind(tb[b + 1]);
+    if (staged_kind(blk)) {
+      const int len = blk.w - blk.z;
+      T g[kStagedSlots];
+#pragma unroll
+      for (int u = 0; u < kStagedSlots; ++u) g[u] = tid + u * kBlock < len ? vec[cur.ix[u]] : T(0);
+      if (pre) staged_load<NT>(idx, val, ptr, tb[b + 1], nxt);
+#pragma unroll
+      for (int u = 0; u < kStagedSlots; ++u) {
+        const int q = tid + u * kBlock;
+        if (q < len) lds[q] = cur.v[u] * g[u];
+      }
+      __syncthreads();
+      T acc = T(0);
+      if (own)
+        for (int q = cur.a0 - blk.z; q < cur.a1 - blk.z; ++q) acc += lds[q];
+      __syncthreads();
+      if (own) out[r] = acc;
+      if (pre) cur = nxt;
+    } else {
+      int a0 = 0, a1 = 0;
+      if (own) { a0 = ptr[r]; a1 = ptr[r + 1]; }
+      const T acc = rb_dot<T, NT>(idx, val, vec, blk.z, blk.w, a0, a1, own, blk.y - blk.x, lds);
+      if (own) out[r] = acc;
+      if (pre) staged_load<NT>(idx, val, ptr, tb[b + 1], cur);
+    }
+  }
+}
+
 // Dual half-step with the long rows split into column panels (plain
 // iterations only).  k_panel_dot reduces each (panel, long row) segment; the
 // blocks of panel p run on XCD p mod 8 (workgroups are dealt to the XCDs in
 // turn), so an XCD gathers from one panel's slice of xbar at a time and the
 // slice stays in its L2.  k_dual_pn then does the short rows as k_dual does and,
 // in extra blocks, the long rows: h = sum of the panel partials in panel order.
+// (One row block per workgroup: these gathers go to L2 and want many waves in
+// flight, more than row_block_run's register budget leaves.)
 template <typename T>
 struct PanelDotArgs {
   const int4* tab; const int32_t* pp; const int32_t* pcol; const T* pval; const T* vec; T* out;
@@ -227,45 +310,6 @@ struct DenseDotArgs {
   T* out; int32_t n;
 };
 
-// A block of short rows (the staged kind of rb_dot) holds at most kRbLds
-// nonzeros: kDenseSlots per thread at stride kBlock.
-constexpr int kDenseSlots = (kRbLds + kBlock - 1) / kBlock;
-
-__device__ __forceinline__ bool staged_kind(int4 blk) {
-  const int nrows = blk.y - blk.x;
-  return nrows > 1 && blk.w - blk.z <= nrows * kRbSerial;
-}
-
-// One staged row block's matrix entries and row pointers, loaded ahead of use.
-template <typename T>
-struct DenseRegs {
-  int ix[kDenseSlots];
-  T v[kDenseSlots];
-  int a0, a1;
-};
-
-template <typename T, bool NT>
-__device__ __forceinline__ void dense_load(const DenseDotArgs<T>& p, int4 blk, DenseRegs<T>& R) {
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int u = 0; u < kDenseSlots; ++u) {
-    const int q = blk.z + tid + u * kBlock;
-    R.ix[u] = 0;
-    R.v[u] = T(0);
-    if (q < blk.w) {
-      R.ix[u] = (int)ld<NT>(p.pcol + q);
-      R.v[u] = ld<NT>(p.pval + q);
-    }
-  }
-  const int r = blk.x + tid;
-  R.a0 = R.a1 = 0;
-  if (r < blk.y) { R.a0 = p.pp[r]; R.a1 = p.pp[r + 1]; }
-}
-
-// The row blocks of a tile run one after another; for the staged kind the
-// next block's entries and row pointers are loaded before the current block
-// is reduced, so their latency overlaps the LDS work.  The sums are those of
-// rb_dot: products staged at their position, each row added serially.
 // (Four waves per SIMD is also what the LDS allows for T = double.)
 template <typename T, bool NT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_dense_dot(DenseDotArgs<T> p) {
@@ -275,40 +319,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
   const int4 tile = p.tiles[blockIdx.x];
   const int c0 = tile.z * kDenseW;
   const int nc = min(kDenseW, p.n - c0);
-  const int nbk = tile.y - tile.x;  // at most kTileBlocks
+  const int nbk = tile.y - tile.x;  // 1 to kTileBlocks
+  if (nbk <= 0) return;             // uniform over the block
   const int tid = threadIdx.x;
+  // the first row block's loads go out with the staging of the slice
+  const int4 blk0 = p.rbx[tile.x];
+  StagedRegs<T> cur;
+  if (staged_kind(blk0)) staged_load<NT>(p.pcol, p.pval, p.pp, blk0, cur);
   if (tid < nbk) tb[tid] = p.rbx[tile.x + tid];
   for (int c = tid; c < nc; c += kBlock) xs[c] = p.vec[c0 + c];
   __syncthreads();
-  DenseRegs<T> cur, nxt;
-  if (nbk > 0 && staged_kind(tb[0])) dense_load<T, NT>(p, tb[0], cur);
-  for (int b = 0; b < nbk; ++b) {  // uniform over the block
-    const int4 blk = tb[b];
-    const int r = blk.x + tid;
-    const bool own = r < blk.y;
-    const bool pre = b + 1 < nbk && staged_kind(tb[b + 1]);
-    if (staged_kind(blk)) {
-      if (pre) dense_load<T, NT>(p, tb[b + 1], nxt);
-#pragma unroll
-      for (int u = 0; u < kDenseSlots; ++u) {
-        const int q = tid + u * kBlock;
-        if (q < blk.w - blk.z) lds[q] = cur.v[u] * xs[cur.ix[u]];
-      }
-      __syncthreads();
-      T acc = T(0);
-      if (own)
-        for (int q = cur.a0 - blk.z; q < cur.a1 - blk.z; ++q) acc += lds[q];
-      __syncthreads();
-      if (own) p.out[r] = acc;
-      if (pre) cur = nxt;
-    } else {
-      int a0 = 0, a1 = 0;
-      if (own) { a0 = p.pp[r]; a1 = p.pp[r + 1]; }
-      const T acc = rb_dot<T, NT>(p.pcol, p.pval, xs, blk.z, blk.w, a0, a1, own, blk.y - blk.x, lds);
-      if (own) p.out[r] = acc;
-      if (pre) dense_load<T, NT>(p, tb[b + 1], cur);
-    }
-  }
+  row_block_run<T, NT>(tb, nbk, p.pcol, p.pval, p.pp, xs, p.out, lds, cur);
 }
 
 // Group sums of kDenseGroup narrow panels, in panel order:
