@@ -299,3 +299,28 @@ def test_more_dense_rows_than_reserved_stay_long():
     ob = np_out(b.solve(tol=0.0, max_iter=70))
     b.close()
     assert rel(oa["x"], ob["x"]) <= 1e-10 and rel(oa["y"], ob["y"]) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("layout", ["plain", "panels"])
+def test_streamed_matrix_loads_change_nothing(layout, precision):
+    """stream_matrix = 1 turns on the non-temporal matrix loads in every
+    half-step kernel (the default only does so above 128 MB of matrix): the
+    iterates are the same bit for bit as with cached loads, with and without
+    the panel and dense-row layouts, in FP64 and in FP32 + refinement."""
+    lp = lpgen.gen(3000, 20000, zipf_alpha=1.3, cap=9000, eq_frac=0.3, free_frac=0.2, values="normal", seed=7)
+    announce(f"streamed matrix loads {layout} precision={precision} nnz={lp.nnz}")
+    eta = oracle_eta(lp)
+    lay = dict(column_panels=16, panel_row_min=8, dense_row_min=512) if layout == "panels" else dict(column_panels=0)
+    outs = []
+    for nt in (0, 1):
+        prob = problem(lp, eta=eta, precision=precision, stream_matrix=nt, **lay)
+        if layout == "panels":
+            assert prob.panels()[1] > 0 and prob.dense()[1] > 0
+        outs.append(np_out(prob.solve(tol=0.0, max_iter=200)))
+        prob.close()
+    assert np.array_equal(outs[0]["x"], outs[1]["x"]) and np.array_equal(outs[0]["y"], outs[1]["y"])
+    assert outs[0]["info"]["restarts"] == outs[1]["info"]["restarts"]
+    if precision == 0:
+        ref = oracle.solve(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, Params(tol=0.0, max_iter=200, eta_override=eta))
+        assert rel(outs[1]["x"], ref.x) <= TOL and rel(outs[1]["y"], ref.y) <= TOL
