@@ -120,8 +120,9 @@ typedef struct {
                               are added in panel order.  When the dense rows hold at
                               least half of the nonzeros, their entries of A~^T are
                               split off the same way for the primal half-step.  At
-                              most 65,536 dense rows (with more, the rows stay long).
-                              0: no dense rows; otherwise > panel_row_min; 4096 */
+                              most 65,536 dense rows (and at most nnz / dense_row_min):
+                              with more, the threshold is doubled until they fit.
+                              0: no dense rows; otherwise > panel_row_min; 2048 */
 } hlp_params;
 
 /* Outcome of a solve.  Objectives and relative errors refer to the original

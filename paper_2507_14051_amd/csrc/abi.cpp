@@ -282,7 +282,7 @@ hlp_err hlp_params_default(hlp_params* p) {
   p->stream_matrix = -1;
   p->column_panels = -1;
   p->panel_row_min = 16;
-  p->dense_row_min = 4096;
+  p->dense_row_min = 2048;
   return HLP_OK;
 }
 
@@ -343,13 +343,16 @@ static hlp_err build_panels(hlp_lp* lp, int32_t P, int32_t T, int32_t Ld, bool a
   if (P <= 0 || lp->m == 0 || lp->n == 0 || lp->nnz == 0) return HLP_OK;
   if (lp->nD_cap == 0) Ld = 0;  // no room reserved for dense rows
   int32_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int attempt = 0; attempt < 2; ++attempt) {
+  // More dense rows than reserved: double the threshold until they fit (a
+  // threshold above n leaves no dense row, so this ends).
+  for (;;) {
     HLP_HIP(launch_panel_split(lp, T, Ld, lp->flags));
     HLP_HIP(hipMemcpyAsync(cnt, lp->flags, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, lp->stream));
     HLP_HIP(hipStreamSynchronize(lp->stream));
-    if (cnt[2] <= lp->nD_cap) break;
-    Ld = 0;  // more dense rows than reserved: they stay long rows
+    if (cnt[2] <= lp->nD_cap || Ld == 0) break;
+    Ld = Ld > lp->n / 2 ? 0 : 2 * Ld;
   }
+  lp->dense_min = Ld;
   const int32_t nL = cnt[0], nD = cnt[2];
   const int64_t nnz_split = lp->nnz - cnt[1];
   if (nL + nD < 1 || nL + nD > lp->nL_cap || nD > lp->nD_cap) return HLP_OK;

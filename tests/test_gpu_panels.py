@@ -199,8 +199,8 @@ def test_panels_automatic_on_large_skewed_lp():
     P, nl = a.panels()
     PD, nd = a.dense()
     lens = np.diff(lp.A.indptr)
-    assert P == 24 and nl == int(((lens > 16) & (lens < 4096)).sum())
-    assert PD == 2442 and nd == int((lens >= 4096).sum()) > 0
+    assert P == 24 and nl == int(((lens > 16) & (lens < 2048)).sum())
+    assert PD == 2442 and nd == int((lens >= 2048).sum()) > 0
     _, _, eta, _ = a.scaling()
     oa = np_out(a.solve(tol=0.0, max_iter=200))
     a.close()
@@ -256,7 +256,7 @@ def test_panels_and_dense_rows_on_c3a_full_size():
     a = problem(lp)
     P, nl = a.panels()
     PD, nd = a.dense()
-    assert P == 24 and nd == int((lens >= 4096).sum()) and nl == int(((lens > 16) & (lens < 4096)).sum())
+    assert P == 24 and nd == int((lens >= 2048).sum()) and nl == int(((lens > 16) & (lens < 2048)).sum())
     _, _, eta, _ = a.scaling()
     oa = np_out(a.solve(tol=0.0, max_iter=130))
     a.close()
@@ -283,15 +283,20 @@ def test_power_iteration_with_panels_matches_oracle():
     assert abs(pit - it) <= 1
 
 
-def test_more_dense_rows_than_reserved_stay_long():
+def test_more_dense_rows_than_reserved_raise_the_threshold():
     """With dense_row_min = 20 the c3b LP has about 100,000 rows above it, more
-    than the 65,536 dense rows the workspace holds: they stay long rows."""
+    than the 65,536 dense rows the workspace holds: the threshold doubles until
+    they fit, and the end point is that of the unsplit layout."""
     lp = lpgen.config("c3b", seed=1)
     lens = np.diff(lp.A.indptr)
     assert (lens >= 20).sum() > 65536
-    announce("panels dense overflow (c3b)")
+    Ld = 20
+    while (lens >= Ld).sum() > 65536:
+        Ld *= 2
+    announce(f"panels dense overflow (c3b): threshold 20 -> {Ld}")
     a = problem(lp, dense_row_min=20)
-    assert a.dense() == (0, 0) and a.panels() == (24, int((lens > 16).sum()))
+    assert a.dense() == (2442, int((lens >= Ld).sum()))
+    assert a.panels() == (24, int(((lens > 16) & (lens < Ld)).sum()))
     _, _, eta, _ = a.scaling()
     oa = np_out(a.solve(tol=0.0, max_iter=70))
     a.close()
