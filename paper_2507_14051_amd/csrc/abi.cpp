@@ -96,7 +96,7 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
     GD = (PD + kDenseGroup - 1) / kDenseGroup;
     nDmax = std::min<int64_t>(std::min<int64_t>(m, nnz / dense_row_min), kMaxDense);
     RD = PD * nDmax;
-    PT = (nDmax + kDenseW - 1) / kDenseW;
+    PT = (nDmax + kDenseWT - 1) / kDenseWT;
     RT = PT * n;
     if (nDmax == 0 || RD + PD + 2 >= (int64_t(1) << 30) || RT + PT + 2 >= (int64_t(1) << 30)) nDmax = RD = PT = RT = 0;
   }
@@ -362,6 +362,7 @@ static hlp_err build_panels(hlp_lp* lp, int32_t P, int32_t T, int32_t Ld, bool a
   lp->nD = nD;
   lp->panel_w = (int32_t)(((int64_t)lp->n + P - 1) / P);
   lp->dense_w = kDenseW;
+  lp->dense_wT = kDenseWT;
   HLP_HIP(launch_panel_layout(lp, lp->flags));
   HLP_HIP(hipMemcpyAsync(cnt, lp->flags, 6 * sizeof(int32_t), hipMemcpyDeviceToHost, lp->stream));
   HLP_HIP(hipStreamSynchronize(lp->stream));
@@ -430,7 +431,7 @@ static hlp_err build_panels(hlp_lp* lp, int32_t P, int32_t T, int32_t Ld, bool a
       HLP_HIP(hipStreamSynchronize(lp->stream));
       return HLP_OK;
     }
-    lp->dense_PT = (nD + lp->dense_w - 1) / lp->dense_w;
+    lp->dense_PT = (nD + lp->dense_wT - 1) / lp->dense_wT;
     HLP_HIP(launch_dense_transpose(lp, lp->flags));
     HLP_HIP(hipMemcpyAsync(cnt, lp->flags, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, lp->stream));
     HLP_HIP(hipStreamSynchronize(lp->stream));

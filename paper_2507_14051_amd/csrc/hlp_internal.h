@@ -116,9 +116,9 @@ struct hlp_lp {
   int32_t nbD = 0, ntilesD = 0, nbCD = 0;
   // The primal side of the dense rows: ATR = A~^T without the dense rows'
   // entries (indices remapped like rowc), ATD = those entries grouped by
-  // slices of dense_w entries of the compact copy of y (row r*n + j = the
+  // slices of dense_wT entries of the compact copy of y (row r*n + j = the
   // entries of column j whose dense index lies in slice r), with its tiles.
-  int32_t dense_PT = 0, dense_PT_cap = 0;
+  int32_t dense_PT = 0, dense_PT_cap = 0, dense_wT = 0;
   int32_t *cpR = nullptr, *rowR = nullptr, *ppT = nullptr;
   uint16_t* rowT = nullptr;  // offset of the dense index in its slice
   double *tvalR = nullptr, *tvalT = nullptr;
@@ -190,6 +190,10 @@ hlp_err hip_fail(hipError_t e, const char* what);
 size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t precision, int32_t panels,
              int32_t panel_row_min, int32_t dense_row_min);
 constexpr int32_t kDenseW = 2048;     // columns per narrow panel (its FP64 slice: 16 KB of LDS; < 65536)
+// Compact dense indices per slice of the primal split (< 65536).  4096 halves
+// the slice partials but its 32 KB slice leaves three blocks per CU, and the
+// primal half-step of the largest LP got slower (2.21 -> 2.29 ms).
+constexpr int32_t kDenseWT = 2048;
 constexpr int32_t kDenseGroup = 64;   // narrow panels summed per group
 constexpr int32_t kTileBlocks = 32;   // row blocks per tile
 constexpr int32_t kMaxDense = 65536;  // dense rows at most (more: no dense class)

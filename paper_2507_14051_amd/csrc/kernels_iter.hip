@@ -310,15 +310,17 @@ struct DenseDotArgs {
   T* out; int32_t n;
 };
 
-// (Four waves per SIMD is also what the LDS allows for T = double.)
-template <typename T, bool NT>
+// W: the slice width (kDenseW columns for AD, kDenseWT dense indices for
+// ATD).  (The register budget is that of four waves per SIMD, at most what
+// the LDS allows for T = double.)
+template <typename T, bool NT, int W>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_dense_dot(DenseDotArgs<T> p) {
-  __shared__ T xs[kDenseW];
+  __shared__ T xs[W];
   __shared__ T lds[kRbLds];
   __shared__ int4 tb[kTileBlocks];
   const int4 tile = p.tiles[blockIdx.x];
-  const int c0 = tile.z * kDenseW;
-  const int nc = min(kDenseW, p.n - c0);
+  const int c0 = tile.z * W;
+  const int nc = min(W, p.n - c0);
   const int nbk = tile.y - tile.x;  // 1 to kTileBlocks
   if (nbk <= 0) return;             // uniform over the block
   const int tid = threadIdx.x;
@@ -977,8 +979,8 @@ hipError_t launch_panel_dual(hlp_lp* lp, const T* pval, const T* pvalD, const T*
   if (lp->nD > 0) {
     DenseDotArgs<T> da{reinterpret_cast<const int4*>(lp->tilesD), reinterpret_cast<const int4*>(lp->rbxD), lp->ppD,
                        lp->pcolD, pvalD, vec, reinterpret_cast<T*>(lp->partD), lp->n};
-    e = lp->nt ? launch_step_kernel(k_dense_dot<T, true>, lp->ntilesD, take(), lp->stream, da)
-               : launch_step_kernel(k_dense_dot<T, false>, lp->ntilesD, take(), lp->stream, da);
+    e = lp->nt ? launch_step_kernel(k_dense_dot<T, true, kDenseW>, lp->ntilesD, take(), lp->stream, da)
+               : launch_step_kernel(k_dense_dot<T, false, kDenseW>, lp->ntilesD, take(), lp->stream, da);
     if (e != hipSuccess) return e;
     const int32_t G = (lp->dense_P + kDenseGroup - 1) / kDenseGroup;
     hipLaunchKernelGGL(k_dense_combine<T>, dim3(lp->nbCD, G), dim3(kBlock), 0, lp->stream,
@@ -1006,8 +1008,8 @@ hipError_t launch_primal_pair(hlp_lp* lp, const T* tvalT, const T* y, const A& a
   last.ev_start = nullptr;
   DenseDotArgs<T> da{reinterpret_cast<const int4*>(lp->tilesT), reinterpret_cast<const int4*>(lp->rbxT2), lp->ppT,
                      lp->rowT, tvalT, y + lp->m + lp->nL, reinterpret_cast<T*>(lp->partT), lp->nD};
-  hipError_t e = lp->nt ? launch_step_kernel(k_dense_dot<T, true>, lp->ntilesT, first, lp->stream, da)
-                        : launch_step_kernel(k_dense_dot<T, false>, lp->ntilesT, first, lp->stream, da);
+  hipError_t e = lp->nt ? launch_step_kernel(k_dense_dot<T, true, kDenseWT>, lp->ntilesT, first, lp->stream, da)
+                        : launch_step_kernel(k_dense_dot<T, false, kDenseWT>, lp->ntilesT, first, lp->stream, da);
   if (e != hipSuccess) return e;
   return launch_step_kernel(kprimal, lp->nbR, last, lp->stream, a);
 }
@@ -1020,7 +1022,7 @@ hipError_t panel_rowsums(hlp_lp* lp, const double* v, double* out) {
   if (lp->nD > 0) {
     DenseDotArgs<double> da{reinterpret_cast<const int4*>(lp->tilesD), reinterpret_cast<const int4*>(lp->rbxD),
                             lp->ppD, lp->pcolD, lp->pvalD, v, lp->partD, lp->n};
-    hipLaunchKernelGGL((k_dense_dot<double, false>), dim3(lp->ntilesD), dim3(kBlock), 0, lp->stream, da);
+    hipLaunchKernelGGL((k_dense_dot<double, false, kDenseW>), dim3(lp->ntilesD), dim3(kBlock), 0, lp->stream, da);
     hipLaunchKernelGGL(k_dense_combine<double>, dim3(lp->nbCD, G), dim3(kBlock), 0, lp->stream,
                        (const double*)lp->partD, lp->nD, lp->dense_P, lp->part2D);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1064,7 +1066,7 @@ hipError_t launch_power_pass_panels(hlp_lp* lp, int64_t* nb) {
   if (lp->ntilesT > 0) {
     DenseDotArgs<double> da{reinterpret_cast<const int4*>(lp->tilesT), reinterpret_cast<const int4*>(lp->rbxT2),
                             lp->ppT, lp->rowT, lp->tvalT, lp->pu + lp->m + lp->nL, lp->partT, lp->nD};
-    hipLaunchKernelGGL((k_dense_dot<double, false>), dim3(lp->ntilesT), dim3(kBlock), 0, lp->stream, da);
+    hipLaunchKernelGGL((k_dense_dot<double, false, kDenseWT>), dim3(lp->ntilesT), dim3(kBlock), 0, lp->stream, da);
     hipLaunchKernelGGL(k_pw_cols, dim3(lp->nbR), dim3(kBlock), 0, lp->stream, reinterpret_cast<const int4*>(lp->rbxR),
                        lp->cpR, lp->rowR, lp->tvalR, (const double*)lp->pu, (const double*)lp->partT, lp->dense_PT,
                        lp->n, lp->pw, lp->partials, (const PowerState*)lp->pstate);

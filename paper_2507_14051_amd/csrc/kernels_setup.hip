@@ -926,13 +926,13 @@ hipError_t launch_dense_transpose(hlp_lp* lp, int32_t* counts) {
   if (lp->nD < 1 || PT < 1 || PT > lp->dense_PT_cap || RT + 1 > lp->rbtmp_rows + 1) return hipErrorInvalidValue;
   const float* t32 = lp->precision == HLP_MIXED ? lp->tval32 : nullptr;
   hipLaunchKernelGGL(k_tr_count, dim3(nblocks((int64_t)n + 1)), dim3(kBlock), 0, s, lp->cp, lp->row, lp->dlid, n,
-                     PT, lp->dense_w, lp->pscrB, lp->pscrA);
+                     PT, lp->dense_wT, lp->pscrB, lp->pscrA);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if ((e = scan_exclusive(lp->pscrB, lp->cpR, (int64_t)n + 1, lp->scan_tmp, s)) != hipSuccess) return e;
   if ((e = scan_exclusive(lp->pscrA, lp->ppT, RT + 1, lp->scan_tmp, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_tr_copy, dim3(nblocks(n)), dim3(kBlock), 0, s, lp->cp, lp->row, lp->tval, t32, lp->dlid,
-                     lp->plid, n, lp->m, lp->dense_w, lp->cpR, lp->ppT, lp->rowR, lp->tvalR,
+                     lp->plid, n, lp->m, lp->dense_wT, lp->cpR, lp->ppT, lp->rowR, lp->tvalR,
                      t32 ? lp->tval32R : nullptr, lp->rowT, lp->tvalT, t32 ? lp->tval32T : nullptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = launch_build_row_blocks(lp, lp->cpR, n, lp->rbR, lp->rbxR, counts + 6)) != hipSuccess) return e;

@@ -116,6 +116,19 @@ def test_panels_dense_rows_wider_than_one_narrow_panel():
     _end_point_case(lp, 130, panels=8, row_min=16, dense_min=1000)
 
 
+def test_panels_primal_split_several_slices():
+    """9,000 dense rows of 40-90 nonzeros (n = 20,000): the primal split takes
+    five slices of the compact y copy, the last one partial, next to a few
+    short rows."""
+    rng = np.random.default_rng(21)
+    m, n = 9500, 20000
+    lens = rng.integers(40, 91, size=m)
+    lens[9000:] = rng.integers(1, 10, size=500)
+    lp = _lp_from_matrix(_random_rows(rng, m, n, lens), seed=21)
+    announce(f"panels primal split, several slices nnz={lp.nnz}")
+    _end_point_case(lp, 130, panels=8, row_min=16, dense_min=32)
+
+
 def test_panels_all_rows_long():
     """panel_row_min below every row length: the short part is empty."""
     lp = lpgen.config("c1", seed=2)
