@@ -51,7 +51,7 @@ typedef enum {
   HLP_EINVAL = -1,       /* invalid argument or input data (message says which) */
   HLP_ENOMEM = -2,       /* workspace or tape too small */
   HLP_EHIP = -3,         /* a HIP runtime call or kernel launch failed */
-  HLP_EUNSUPPORTED = -4  /* valid input outside what this build supports */
+  HLP_EUNSUPPORTED = -4  /* valid input outside what the library supports */
 } hlp_err;
 
 typedef enum {

@@ -140,3 +140,30 @@ def test_differentiation_workload_full_size():
     announce(f"adjoint FD full c5 m={lp.m} n={lp.n} nnz={lp.nnz} K=2000 ckpt=100")
     fd, an = _fd_check(lp, 2000, 100, 1)
     assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
+
+
+def test_envelope_theorem_at_convergence():
+    """Warm-started at the oracle's 1e-10 solution, the GPU derivative of
+    c^T x_K with respect to c tends to x*, and that with respect to an equality
+    row's right-hand side to y* (the envelope theorem for the optimal value;
+    unique optimum).  The bar is the oracle's own envelope test's."""
+    from paper_2507_14051_amd.autograd import PDHGUnrolled
+    import oracle
+    lp = lpgen.config("c1", seed=2, scale=0.1)
+    announce(f"adjoint envelope theorem m={lp.m} n={lp.n}")
+    sol = oracle.solve(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, Params(tol=1e-10))
+    assert sol.status == oracle.pdhg.OPTIMAL
+    prob = problem(lp, eta=oracle_eta(lp))
+    dev = "cuda:0"
+    ts = [torch.tensor(getattr(lp, k), dtype=torch.float64, device=dev, requires_grad=True) for k in KEYS]
+    x0 = torch.tensor(sol.x, dtype=torch.float64, device=dev)
+    y0 = torch.tensor(sol.y, dtype=torch.float64, device=dev)
+    x, y = PDHGUnrolled.apply(*ts, prob, 400, 50, None, x0, y0)
+    (ts[0] * x).sum().backward()            # c^T x_K: direct term plus the reverse pass
+    g = _eq_sum({k: t.grad.cpu().numpy() for k, t in zip(KEYS, ts)}, lp)
+    prob.close()
+    assert np.abs(g["c"] - sol.x).max() <= 1e-3 * (1 + np.abs(sol.x).max())
+    eq = lp.lc == lp.uc
+    assert eq.sum() > 0
+    assert np.abs(g["lc"][eq] - sol.y[eq]).max() <= 1e-3 * (1 + np.abs(sol.y).max())
+    print(f"envelope: |dc - x*| {np.abs(g['c'] - sol.x).max():.1e}, |db - y*| {np.abs(g['lc'][eq] - sol.y[eq]).max():.1e}")
