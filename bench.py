@@ -96,7 +96,7 @@ def measure_hbm(dev, name="c3b", iters=640):
     import torch
 
     import lpgen
-    from paper_2507_14051_amd import Problem
+    from paper_2507_14051_amd import MIXED, Problem
 
     t0 = time.perf_counter()
     lp3 = lpgen.config(name, seed=1, progress=lambda k, n: log(f"# {name}: rows chunk {k}/{n}") if k % 8 == 0 else None)
@@ -108,7 +108,6 @@ def measure_hbm(dev, name="c3b", iters=640):
     p3 = Problem(lp3.A, lp3.c, lp3.lc, lp3.uc, lp3.lv, lp3.uv, device=dev)
     torch.cuda.synchronize()
     s3 = time.perf_counter() - t0
-    del lp3
     panels = p3.panels()
     dense = p3.dense()
     _, _, _, power_iters = p3.scaling()
@@ -130,7 +129,22 @@ def measure_hbm(dev, name="c3b", iters=640):
            "dual_gbs": round(db3 / (pr3["dual_ms"] * 1e-3) / 1e9, 1),
            "iter_gbs": round((pb3 + db3) / (pr3["iter_ms"] * 1e-3) / 1e9, 1)}
     hbm["iter_frac_of_peak"] = round(hbm["iter_gbs"] / HBM_PEAK_GBS, 4)
+    eta3 = p3.scaling()[2]
     p3.close()
+    # the same plain iterations in FP32 (mixed precision: FP32 matrix copies
+    # and iterates, FP64 refinement at restarts), same stepsize
+    pm = Problem(lp3.A, lp3.c, lp3.lc, lp3.uc, lp3.lv, lp3.uv, device=dev, precision=MIXED, eta_override=eta3)
+    del lp3
+    pm.solve(max_iter=64, tol=0.0, want_r=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pm.solve(max_iter=iters, tol=0.0, want_r=False)
+    torch.cuda.synchronize()
+    itm = iters / (time.perf_counter() - t0)
+    prm = pm.profile(iters=min(100, iters))
+    pm.close()
+    hbm["fp32"] = {"iters_per_s": round(itm, 1), "speedup_vs_fp64": round(itm / it_s, 3),
+                   "primal_us": round(prm["primal_ms"] * 1e3, 2), "dual_us": round(prm["dual_ms"] * 1e3, 2)}
     log(f"# hbm: {hbm}")
     return hbm
 
