@@ -1103,8 +1103,8 @@ hipError_t launch_primal(hlp_lp* lp, const StepArgs& s) {
   PrimalArgs a{reinterpret_cast<const int4*>(lp->rbxT), lp->cp, lp->row, lp->tval, lp->y, lp->x, lp->xa, lp->ct, lp->lvt, lp->uvt,
                lp->xbar, lp->xh, lp->dxv, region(lp, R_PRIMAL), s.mask_x, lp->step, s.j};
   if (s.mask_x) return launch_step_kernel(k_primal<2, false>, lp->nbT, s, lp->stream, a);
-  if (s.residual) return launch_step_kernel(k_primal<1, false>, lp->nbT, s, lp->stream, a);
-  if (lp->panels && lp->ntilesT > 0) {
+  const bool split = lp->panels && lp->ntilesT > 0;
+  if (split) {
     // dense rows' part first (slices of y staged in LDS), then the rest
     a.rb = reinterpret_cast<const int4*>(lp->rbxR);
     a.cp = lp->cpR;
@@ -1113,8 +1113,13 @@ hipError_t launch_primal(hlp_lp* lp, const StepArgs& s) {
     a.partT = lp->partT;
     a.PT = lp->dense_PT;
     a.n = lp->n;
-    return launch_primal_pair(lp, lp->tvalT, lp->y, a, lp->nt ? k_primal<0, true> : k_primal<0, false>, s);
   }
+  if (s.residual) {
+    lp->nb_primal_region = split ? lp->nbR : lp->nbT;
+    if (split) return launch_primal_pair(lp, lp->tvalT, lp->y, a, k_primal<1, false>, s);
+    return launch_step_kernel(k_primal<1, false>, lp->nbT, s, lp->stream, a);
+  }
+  if (split) return launch_primal_pair(lp, lp->tvalT, lp->y, a, lp->nt ? k_primal<0, true> : k_primal<0, false>, s);
   if (lp->panels) a.row = lp->rowc;  // long rows' y entries from the compact copy
   if (lp->nt) return launch_step_kernel(k_primal<0, true>, lp->nbT, s, lp->stream, a);
   return launch_step_kernel(k_primal<0, false>, lp->nbT, s, lp->stream, a);
@@ -1168,7 +1173,8 @@ hipError_t launch_finalize(hlp_lp* lp, int32_t which, int32_t slot) {
   int nr = 0;
   const bool f32 = (which & 16) != 0;
   const int64_t nbp = lp->nbT, nbd = lp->nb_dual_region > 0 ? lp->nb_dual_region : lp->nbA;
-  if (which & 1) a.r[nr++] = make_region(region(lp, R_PRIMAL), nbp, {Q_DX2, Q_XA2}, 0u);
+  const int64_t nbx = lp->nb_primal_region > 0 ? lp->nb_primal_region : lp->nbT;
+  if (which & 1) a.r[nr++] = make_region(region(lp, R_PRIMAL), nbx, {Q_DX2, Q_XA2}, 0u);
   if (which & 2) {
     if (f32) a.r[nr++] = make_region(region(lp, R_DUAL), nbd, {Q_DY2, Q_DYADX, Q_YA2}, 0u);
     else a.r[nr++] = make_region(region(lp, R_DUAL), nbd, {Q_DY2, Q_DYADX, Q_YA2, Q_RP2, Q_DOBJ_R}, 0u);
@@ -1247,7 +1253,10 @@ hipError_t launch_primal32(hlp_lp* lp, const StepArgs& s) {
   if (lp->nbT == 0) return hipSuccess;
   Primal32Args a{reinterpret_cast<const int4*>(lp->rbxT), lp->cp, lp->row, lp->tval32, lp->y32, lp->x32, lp->xa32, lp->c32, lp->lv32, lp->uv32,
                  lp->xbar32, lp->xh32, lp->dx32, region(lp, R_PRIMAL), lp->step, s.j};
-  if (s.residual) return launch_step_kernel(k_primal32<true, false>, lp->nbT, s, lp->stream, a);
+  if (s.residual) {
+    lp->nb_primal_region = lp->nbT;
+    return launch_step_kernel(k_primal32<true, false>, lp->nbT, s, lp->stream, a);
+  }
   if (lp->panels && lp->ntilesT > 0) {
     a.rb = reinterpret_cast<const int4*>(lp->rbxR);
     a.cp = lp->cpR;
