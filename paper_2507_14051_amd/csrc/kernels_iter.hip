@@ -216,16 +216,17 @@ __device__ __forceinline__ void staged_load(const I* __restrict__ idx, const T* 
   if (r < blk.y) { R.a0 = ptr[r]; R.a1 = ptr[r + 1]; }
 }
 
-// tb: the nbk row blocks (in LDS); out[r] = row r's sum of val .* vec[idx].
+// tb: the nbk row blocks (in LDS); out[r] = row r's sum of val .* vec[idx],
+// products and sums in T (the values and the vector are V).
 // cur: the first block's loads if it is of the staged kind (the caller issues
 // them, so they can overlap its own set-up).
-template <typename T, bool NT, typename I>
+template <typename T, bool NT, typename I, typename V>
 __device__ __forceinline__ void row_block_run(const int4* tb, int nbk, const I* __restrict__ idx,
-                                              const T* __restrict__ val, const int32_t* __restrict__ ptr,
-                                              const T* __restrict__ vec, T* __restrict__ out, T* lds,
-                                              StagedRegs<T>& cur) {
+                                              const V* __restrict__ val, const int32_t* __restrict__ ptr,
+                                              const V* __restrict__ vec, T* __restrict__ out, T* lds,
+                                              StagedRegs<V>& cur) {
   const int tid = threadIdx.x;
-  StagedRegs<T> nxt;
+  StagedRegs<V> nxt;
   for (int b = 0; b < nbk; ++b) {  // uniform over the workgroup
     const int4 blk = tb[b];
     const int r = blk.x + tid;
@@ -233,14 +234,14 @@ __device__ __forceinline__ void row_block_run(const int4* tb, int nbk, const I* 
     const bool pre = b + 1 < nbk && staged_kind(tb[b + 1]);
     if (staged_kind(blk)) {
       const int len = blk.w - blk.z;
-      T g[kStagedSlots];
+      V g[kStagedSlots];
 #pragma unroll
-      for (int u = 0; u < kStagedSlots; ++u) g[u] = tid + u * kBlock < len ? vec[cur.ix[u]] : T(0);
+      for (int u = 0; u < kStagedSlots; ++u) g[u] = tid + u * kBlock < len ? vec[cur.ix[u]] : V(0);
       if (pre) staged_load<NT>(idx, val, ptr, tb[b + 1], nxt);
 #pragma unroll
       for (int u = 0; u < kStagedSlots; ++u) {
         const int q = tid + u * kBlock;
-        if (q < len) lds[q] = cur.v[u] * g[u];
+        if (q < len) lds[q] = (T)cur.v[u] * (T)g[u];
       }
       __syncthreads();
       T acc = T(0);
@@ -267,14 +268,15 @@ __device__ __forceinline__ void row_block_run(const int4* tb, int nbk, const I* 
 // in extra blocks, the long rows: h = sum of the panel partials in panel order.
 // (One row block per workgroup: these gathers go to L2 and want many waves in
 // flight, more than row_block_run's register budget leaves.)
-template <typename T>
+// (T: products and sums; V: the values and the vector.)
+template <typename T, typename V = T>
 struct PanelDotArgs {
-  const int4* tab; const int32_t* pp; const int32_t* pcol; const T* pval; const T* vec; T* out;
+  const int4* tab; const int32_t* pp; const int32_t* pcol; const V* pval; const V* vec; T* out;
   int32_t off[9];
 };
 
-template <typename T, bool NT>
-__global__ __launch_bounds__(kBlock) void k_panel_dot(PanelDotArgs<T> p) {
+template <typename T, bool NT, typename V = T>
+__global__ __launch_bounds__(kBlock) void k_panel_dot(PanelDotArgs<T, V> p) {
   __shared__ T lds[kRbLds];
   const int x = blockIdx.x & 7;
   const int k = p.off[x] + (int)(blockIdx.x >> 3);
@@ -304,18 +306,18 @@ __device__ __forceinline__ T panel_sum(const T* __restrict__ part, int32_t P, in
 // Dense rows: a tile is up to kTileBlocks row blocks of one narrow panel of
 // AD; the block stages the panel's slice of the vector in LDS once and
 // gathers from there (the indices are 16-bit offsets in the slice).
-template <typename T>
+template <typename T, typename V = T>
 struct DenseDotArgs {
-  const int4* tiles; const int4* rbx; const int32_t* pp; const uint16_t* pcol; const T* pval; const T* vec;
+  const int4* tiles; const int4* rbx; const int32_t* pp; const uint16_t* pcol; const V* pval; const V* vec;
   T* out; int32_t n;
 };
 
 // W: the slice width (kDenseW columns for AD, kDenseWT dense indices for
 // ATD).  (The register budget is that of four waves per SIMD, at most what
 // the LDS allows for T = double.)
-template <typename T, bool NT, int W>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_dense_dot(DenseDotArgs<T> p) {
-  __shared__ T xs[W];
+template <typename T, bool NT, int W, typename V = T>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_dense_dot(DenseDotArgs<T, V> p) {
+  __shared__ V xs[W];
   __shared__ T lds[kRbLds];
   __shared__ int4 tb[kTileBlocks];
   const int4 tile = p.tiles[blockIdx.x];
@@ -326,7 +328,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
   const int tid = threadIdx.x;
   // the first row block's loads go out with the staging of the slice
   const int4 blk0 = p.rbx[tile.x];
-  StagedRegs<T> cur;
+  StagedRegs<V> cur;
   if (staged_kind(blk0)) staged_load<NT>(p.pcol, p.pval, p.pp, blk0, cur);
   if (tid < nbk) tb[tid] = p.rbx[tile.x + tid];
   for (int c = tid; c < nc; c += kBlock) xs[c] = p.vec[c0 + c];
@@ -425,12 +427,14 @@ __global__ __launch_bounds__(kBlock) void k_dual_pn(DualPanelArgs p) {
 // Check iterations with panels: the long and dense rows' sums of one product
 // (out[l] for long row l, out[nL + d] for dense row d), from the partials of
 // the panel kernels, in the same order as k_dual_pn.
-__global__ __launch_bounds__(kBlock) void k_pn_rowsums(const double* __restrict__ part,
-                                                      const double* __restrict__ part2, int32_t P, int32_t nL,
-                                                      int32_t nD, int32_t G, double* __restrict__ out) {
+// (T: the partials' type, summed in T as the half-steps do; out in FP64.)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pn_rowsums(const T* __restrict__ part, const T* __restrict__ part2,
+                                                      int32_t P, int32_t nL, int32_t nD, int32_t G,
+                                                      double* __restrict__ out) {
   const int l = blockIdx.x * kBlock + threadIdx.x;
-  if (l < nL) out[l] = panel_sum(part, P, nL, l);
-  else if (l < nL + nD) out[l] = group_sum(part2, G, nD, l - nL);
+  if (l < nL) out[l] = (double)panel_sum(part, P, nL, l);
+  else if (l < nL + nD) out[l] = (double)group_sum(part2, G, nD, l - nL);
 }
 
 // The check-iteration dual half-step with panels: h = A~ xbar, A~ dx and
@@ -493,6 +497,113 @@ __global__ __launch_bounds__(kBlock) void k_dual_pn_res(DualResArgs p) {
     q[4] = (finite(lo) ? lo * fmax(yh, 0.0) : 0.0) - (finite(hi) ? hi * fmax(-yh, 0.0) : 0.0);
   }
   block_reduce_store<5>(q, p.partials + (int64_t)blockIdx.x * kRegionStride);
+}
+
+// The FP32 path's check-iteration dual half-step with panels: h in FP32 and
+// A~ dx accumulated in FP64 (as k_dual32's check variant computes them) from
+// AS for the short rows and from the row sums for the others; the update,
+// yhat, the restart partials and the compact copy.
+struct Dual32ResArgs {
+  const int4* rb; const int32_t* sp; const int32_t* scol; const float* sval;
+  const float* xbar; const float* dx;
+  float* y; const float* ya; const float* lc; const float* uc; const float* b;
+  float* yh; double* partials; const StepDev* step;
+  const uint32_t* lbits; const int32_t* lrow; const double* rsum;
+  int32_t nbS, j, m, nL, nD;
+};
+
+__global__ __launch_bounds__(kBlock) void k_dual32_pn_res(Dual32ResArgs p) {
+  __shared__ double lds[kRbLds];
+  int i = 0, l = -1;
+  bool own = false;
+  float h = 0.0f, yi = 0.0f, lo = 0.0f, hi = 0.0f, yai = 0.0f, bi = 0.0f;
+  double adx = 0.0;
+  if ((int)blockIdx.x < p.nbS) {
+    const int4 blk = p.rb[blockIdx.x];
+    i = blk.x + threadIdx.x;
+    const bool in = i < blk.y;
+    int a0 = 0, a1 = 0;
+    if (in) {
+      a0 = p.sp[i]; a1 = p.sp[i + 1];
+      own = !is_long(p.lbits, i);
+      if (own) { yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i]; bi = p.b[i]; }
+    }
+    const int nr = blk.y - blk.x;
+    h = rb_dot<float>(p.scol, p.sval, p.xbar, blk.z, blk.w, a0, a1, in, nr, reinterpret_cast<float*>(lds));
+    adx = rb_dot<double>(p.scol, p.sval, p.dx, blk.z, blk.w, a0, a1, in, nr, lds);
+  } else {
+    l = ((int)blockIdx.x - p.nbS) * kBlock + threadIdx.x;
+    const int nc = p.nL + p.nD;
+    own = l < nc;
+    if (own) {
+      i = p.lrow[l];
+      yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i]; bi = p.b[i];
+      h = (float)p.rsum[l];
+      adx = p.rsum[nc + l];
+    }
+  }
+  double q[3] = {0.0, 0.0, 0.0};
+  if (own) {
+    const float sigma = (float)p.step->sigma, gam = (float)p.step->gamma, a = (float)halpern_a(p.step, p.j);
+    const float w = h - (bi + yi) / sigma;
+    const float yh = yi + sigma * (clampv(w, lo, hi) - h);
+    const float yn = a * ((1.0f + gam) * yh - gam * yi) + (1.0f - a) * yai;
+    p.y[i] = yn;
+    if (l >= 0) p.y[p.m + l] = yn;
+    p.yh[i] = yh;
+    const double dy = (double)(yi - yh);
+    q[0] = dy * dy;
+    q[1] = dy * adx;
+    const double e2 = (double)(yh - yai);
+    q[2] = e2 * e2;
+  }
+  block_reduce_store<3>(q, p.partials + (int64_t)blockIdx.x * kRegionStride);
+}
+
+// Row side of the KKT error (mixed mode, FP64) with panels: A~ xh from AS for
+// the short rows and from the row sums for the long and dense rows.
+struct KktRowPanelArgs {
+  const int4* rb; const int32_t* sp; const int32_t* scol; const double* sval;
+  const double* xh; const double* yh; const double* lc; const double* uc; const double* dr;
+  double* ax_out; double* partials; const uint32_t* lbits; const int32_t* lrow; const double* rsum;
+  int32_t nbS, nL, nD;
+};
+
+__global__ __launch_bounds__(kBlock) void k_kkt_rows_pn(KktRowPanelArgs p) {
+  __shared__ double lds[kRbLds];
+  int i = 0;
+  bool own = false;
+  double acc = 0.0;
+  if ((int)blockIdx.x < p.nbS) {
+    const int4 blk = p.rb[blockIdx.x];
+    i = blk.x + threadIdx.x;
+    const bool in = i < blk.y;
+    int a0 = 0, a1 = 0;
+    if (in) {
+      a0 = p.sp[i]; a1 = p.sp[i + 1];
+      own = !is_long(p.lbits, i);
+    }
+    acc = rb_dot<double>(p.scol, p.sval, p.xh, blk.z, blk.w, a0, a1, in, blk.y - blk.x, lds);
+  } else {
+    const int l = ((int)blockIdx.x - p.nbS) * kBlock + threadIdx.x;
+    own = l < p.nL + p.nD;
+    if (own) {
+      i = p.lrow[l];
+      acc = p.rsum[l];
+    }
+  }
+  double q[3] = {0.0, 0.0, 0.0};
+  if (own) {
+    const double lo = p.lc[i], hi = p.uc[i];
+    const double viol = acc - clampv(acc, lo, hi);
+    const double pr = viol / p.dr[i];
+    q[0] = pr * pr;
+    const double yh = p.yh[i];
+    q[1] = (finite(lo) ? lo * fmax(yh, 0.0) : 0.0) - (finite(hi) ? hi * fmax(-yh, 0.0) : 0.0);
+    q[2] = fabs(viol);
+    p.ax_out[i] = acc;
+  }
+  block_reduce_store<3>(q, p.partials + (int64_t)blockIdx.x * kRegionStride, 4u);
 }
 
 // Power iteration with panels (setup): w = A~ v from AS for the short rows
@@ -1015,26 +1126,51 @@ hipError_t launch_primal_pair(hlp_lp* lp, const T* tvalT, const T* y, const A& a
 }
 
 // The panel pipeline of one product A~ v for the long and dense rows, into
-// out[0, nL + nD) (no events).
-hipError_t panel_rowsums(hlp_lp* lp, const double* v, double* out) {
+// out[0, nL + nD) (no events): products and sums in T over values and a
+// vector of type V (pval, pvalD: the AP and AD values of that type).
+template <typename T, typename V>
+hipError_t panel_rowsums_t(hlp_lp* lp, const V* pval, const V* pvalD, const V* v, double* out) {
   hipError_t e;
   const int32_t G = (lp->dense_P + kDenseGroup - 1) / kDenseGroup;
+  T* partD = reinterpret_cast<T*>(lp->partD);
+  T* part2D = reinterpret_cast<T*>(lp->part2D);
+  T* ppart = reinterpret_cast<T*>(lp->ppart);
   if (lp->nD > 0) {
-    DenseDotArgs<double> da{reinterpret_cast<const int4*>(lp->tilesD), reinterpret_cast<const int4*>(lp->rbxD),
-                            lp->ppD, lp->pcolD, lp->pvalD, v, lp->partD, lp->n};
-    hipLaunchKernelGGL((k_dense_dot<double, false, kDenseW>), dim3(lp->ntilesD), dim3(kBlock), 0, lp->stream, da);
-    hipLaunchKernelGGL(k_dense_combine<double>, dim3(lp->nbCD, G), dim3(kBlock), 0, lp->stream,
-                       (const double*)lp->partD, lp->nD, lp->dense_P, lp->part2D);
+    DenseDotArgs<T, V> da{reinterpret_cast<const int4*>(lp->tilesD), reinterpret_cast<const int4*>(lp->rbxD),
+                          lp->ppD, lp->pcolD, pvalD, v, partD, lp->n};
+    hipLaunchKernelGGL((k_dense_dot<T, false, kDenseW, V>), dim3(lp->ntilesD), dim3(kBlock), 0, lp->stream, da);
+    hipLaunchKernelGGL(k_dense_combine<T>, dim3(lp->nbCD, G), dim3(kBlock), 0, lp->stream, (const T*)partD, lp->nD,
+                       lp->dense_P, part2D);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (lp->nL > 0) {
-    PanelDotArgs<double> pa{reinterpret_cast<const int4*>(lp->tabP), lp->pp, lp->pcol, lp->pval, v, lp->ppart, {}};
+    PanelDotArgs<T, V> pa{reinterpret_cast<const int4*>(lp->tabP), lp->pp, lp->pcol, pval, v, ppart, {}};
     for (int k = 0; k < 9; ++k) pa.off[k] = lp->poff[k];
-    hipLaunchKernelGGL((k_panel_dot<double, false>), dim3(lp->nbPgrid), dim3(kBlock), 0, lp->stream, pa);
+    hipLaunchKernelGGL((k_panel_dot<T, false, V>), dim3(lp->nbPgrid), dim3(kBlock), 0, lp->stream, pa);
   }
-  hipLaunchKernelGGL(k_pn_rowsums, dim3(nblocks((int64_t)lp->nL + lp->nD)), dim3(kBlock), 0, lp->stream,
-                     (const double*)lp->ppart, (const double*)lp->part2D, lp->panels, lp->nL, lp->nD, G, out);
+  hipLaunchKernelGGL(k_pn_rowsums<T>, dim3(nblocks((int64_t)lp->nL + lp->nD)), dim3(kBlock), 0, lp->stream,
+                     (const T*)ppart, (const T*)part2D, lp->panels, lp->nL, lp->nD, G, out);
   return hipGetLastError();
+}
+
+hipError_t panel_rowsums(hlp_lp* lp, const double* v, double* out) {
+  return panel_rowsums_t<double, double>(lp, lp->pval, lp->pvalD, v, out);
+}
+
+// The FP32 path's check dual half-step with panels: h as the plain FP32
+// panel half-step sums it (FP32 partials in panel order), A~ dx in FP64.
+hipError_t launch_dual32_res_panels(hlp_lp* lp, const StepArgs& s) {
+  const int64_t nc = (int64_t)lp->nL + lp->nD;
+  hipError_t e;
+  if ((e = panel_rowsums_t<float, float>(lp, lp->pval32, lp->pval32D, lp->xbar32, lp->rsum)) != hipSuccess) return e;
+  if ((e = panel_rowsums_t<double, float>(lp, lp->pval32, lp->pval32D, lp->dx32, lp->rsum + nc)) != hipSuccess)
+    return e;
+  Dual32ResArgs d{reinterpret_cast<const int4*>(lp->rbxS), lp->sp, lp->scol, lp->sval32, lp->xbar32, lp->dx32,
+                  lp->y32, lp->ya32, lp->lc32, lp->uc32, lp->b32, lp->yh32, region(lp, R_DUAL), lp->step,
+                  lp->lbits, lp->lrow, lp->rsum, lp->nbS, s.j, lp->m, lp->nL, lp->nD};
+  const int32_t nb = lp->nbS + (int32_t)((nc + kBlock - 1) / kBlock);
+  lp->nb_dual_region = nb;
+  return launch_step_kernel(k_dual32_pn_res, nb, s, lp->stream, d);
 }
 
 hipError_t launch_dual_res_panels(hlp_lp* lp, const StepArgs& s) {
@@ -1159,6 +1295,19 @@ hipError_t launch_kkt_cols(hlp_lp* lp, double* r_out) {
 
 hipError_t launch_kkt_rows(hlp_lp* lp) {
   if (lp->nbA == 0) return hipSuccess;
+  if (lp->panels) {
+    const int64_t nc = (int64_t)lp->nL + lp->nD;
+    hipError_t e = panel_rowsums(lp, lp->xh, lp->rsum);
+    if (e != hipSuccess) return e;
+    KktRowPanelArgs a{reinterpret_cast<const int4*>(lp->rbxS), lp->sp, lp->scol, lp->sval, lp->xh, lp->yh,
+                      lp->lct, lp->uct, lp->dr, lp->axc, region(lp, R_ROWS), lp->lbits, lp->lrow, lp->rsum,
+                      lp->nbS, lp->nL, lp->nD};
+    const int32_t nb = lp->nbS + (int32_t)((nc + kBlock - 1) / kBlock);
+    lp->nb_rows_region = nb;
+    hipLaunchKernelGGL(k_kkt_rows_pn, dim3(nb), dim3(kBlock), 0, lp->stream, a);
+    return hipGetLastError();
+  }
+  lp->nb_rows_region = lp->nbA;
   KktRowArgs a{lp->rbA, lp->rp, lp->col, lp->val, lp->xh, lp->yh, lp->lct, lp->uct, lp->dr, lp->axc,
                region(lp, R_ROWS)};
   hipLaunchKernelGGL(k_kkt_rows, dim3(lp->nbA), dim3(kBlock), 0, lp->stream, a);
@@ -1184,7 +1333,8 @@ hipError_t launch_finalize(hlp_lp* lp, int32_t which, int32_t slot) {
       a.r[nr++] = make_region(region(lp, R_KKT), nbp, {Q_RD2, Q_DOBJ_C, Q_POBJ, Q_VD, Q_VX}, 8u | 16u);
     else a.r[nr++] = make_region(region(lp, R_KKT), nbp, {Q_RD2, Q_DOBJ_C, Q_POBJ}, 0u);
   }
-  if (which & 8) a.r[nr++] = make_region(region(lp, R_ROWS), lp->nbA, {Q_RP2, Q_DOBJ_R, Q_VP}, 4u);
+  const int64_t nbr = lp->nb_rows_region > 0 ? lp->nb_rows_region : lp->nbA;
+  if (which & 8) a.r[nr++] = make_region(region(lp, R_ROWS), nbr, {Q_RP2, Q_DOBJ_R, Q_VP}, 4u);
   if (nr == 0) return hipSuccess;
   int64_t nbmax = 0;
   for (int r = 0; r < nr; ++r) nbmax = std::max(nbmax, a.r[r].nb);
@@ -1278,6 +1428,7 @@ hipError_t launch_dual32(hlp_lp* lp, const StepArgs& s) {
   Dual32Args a{reinterpret_cast<const int4*>(lp->rbxA), lp->rp, lp->col, lp->val32, lp->xbar32, lp->dx32, lp->y32, lp->ya32, lp->lc32, lp->uc32,
                lp->b32, lp->yh32, region(lp, R_DUAL), lp->step, s.j};
   if (s.residual) {
+    if (lp->panels) return launch_dual32_res_panels(lp, s);
     lp->nb_dual_region = lp->nbA;
     hipError_t e = launch_step_kernel(k_dual32<true, false>, lp->nbA, s, lp->stream, a);
     return e != hipSuccess ? e : refresh_long_y(lp, lp->y32);
