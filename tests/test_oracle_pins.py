@@ -18,6 +18,7 @@ import oracle
 from oracle.brute import brute_force
 from oracle.kkt import kkt
 from oracle.pdhg import Params, pdhg_operator, pid_update, power_norm, rescale, restart_decision
+from tests import _pins
 from tests._highs import highs
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -132,14 +133,9 @@ def test_diagonal_lp_separable():
 
 
 def test_kkt_hand_example():
-    g = json.load(open(os.path.join(HERE, "golden", "kkt_2x2.json")))
-    f = lambda v: np.array([float(t) for t in v])
-    A = sp.csr_matrix(np.array(g["A"]))
-    for case in g["cases"]:
-        k = kkt(A, f(g["c"]), f(g["lc"]), f(g["uc"]), f(case["lv"]), f(case["uv"]), f(g["x"]), f(g["y"]))
-        for key in ("pobj", "dobj", "rho_p", "rho_d", "rel_gap", "rel_primal", "rel_dual", "rel_kkt"):
-            assert k[key] == pytest.approx(case[key], rel=1e-14, abs=1e-15), (case["name"], key)
-        np.testing.assert_allclose(k["r"], case["r"], rtol=0, atol=0)
+    """tests/golden/kkt_2x2.json: hand-computed KKT parts, including a case with
+    objectives of the same sign (fixes the gap's denominator)."""
+    _pins.pin_kkt_golden(oracle)
 
 
 # ------------------------------------------------------------------ invariants of the operator
@@ -308,3 +304,35 @@ def test_validation_rejects(bad):
         uv[1] = -np.inf
     with pytest.raises(ValueError):
         oracle.solve(A, c, lc, uc, lv, uv)
+
+
+# ------------------------------------------------------------------ definitions and hand arithmetic (tests/_pins.py)
+@pytest.mark.parametrize("pin", [p for p in _pins.ALL_PINS if p is not _pins.pin_kkt_golden],
+                         ids=lambda p: p.__name__)
+def test_pin(pin):
+    """r(z) against the dense P of Sec. 2.2; the reflected Halpern closed form;
+    hand-computed restart schedules and epoch bookkeeping; hand-computed
+    Ruiz / Pock-Chambolle factors."""
+    pin(oracle)
+
+
+def test_flipped_P_breaks_firm_nonexpansiveness():
+    """The firm-nonexpansiveness pin can tell the sign of P's off-diagonal
+    blocks: with -A in place of A it fails on some random pair."""
+    lp = lpgen.gen_mixed(30, 40, rowlen=3, seed=4)
+    A, AT = _identity_scaled(lp)
+    n = lp.n
+    eta = 0.998 / np.linalg.norm(A.toarray(), 2)
+    rng = np.random.default_rng(0)
+    violated = 0
+    for trial in range(100):
+        omega = math.exp(rng.uniform(-2, 2))
+        z1 = rng.standard_normal(n + lp.m) * 3
+        z2 = rng.standard_normal(n + lp.m) * 3
+        T = lambda z: np.concatenate(pdhg_operator(A, AT, lp.c, lp.lv, lp.uv, lp.lc, lp.uc,
+                                                   eta / omega, eta * omega, z[:n], z[n:])[:2])
+        d = T(z1) - T(z2)
+        lhs = _pnorm_inner(-A, eta, omega, d, d, n)
+        rhs = _pnorm_inner(-A, eta, omega, d, z1 - z2, n)
+        violated += lhs > rhs + 1e-9 * abs(rhs)
+    assert violated > 0
