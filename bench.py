@@ -2,21 +2,30 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Workload (one "step"): one full solve of the medium synthetic LP
-(m=100,000, n=200,000, 8 nonzeros per row at uniform random columns, N(0,1)
-values, 30% equality rows, 20% of the columns free above) to 1e-8 relative KKT
-error in FP64, inputs resident in HBM and the handle set up (transpose,
-rescaling, power iteration) before the timed region.  ``value`` is PDHG
-iterations per second over the timed steps.  The same run also reports the
-setup time, the FP32 + refinement solve of the same LP to 1e-8, the dominant
-kernel against the HBM roofline (HIP events on the library's stream), the
-HBM-bound skewed LP (m=2e6, n=5e6, Zipf row lengths, ~3e7 nonzeros) and the
-FP64 CPU oracle on a bounded sample of the medium LP.  Prints ONE JSON line.
+Headline workload: the largest configuration, the skewed LP with the literal
+row-length law (m=2,000,000, n=5,000,000, Zipf(1.5) row lengths capped at
+50,000 -- 692M nonzeros, 7,007 rows at the cap -- values sign * 10^U[-3,3],
+30% equality rows, 20% of the columns free above), in FP64, inputs resident
+in HBM and the handle set up (transpose, rescaling, power iteration) before
+the timed region.  One step is one FP64 solve from the all-zero start with
+the paper's settings and tolerance 1e-8, capped at --step-iters PDHG
+iterations (every 64 iterations a check: fixed-point residual, relative KKT,
+restart tests, PID update).  ``value`` is PDHG iterations per second over the
+timed steps.
 
-    python bench.py --kernels-only
+The same run reports, for the headline LP, one solve under a time limit in
+FP64 and in FP32 with refinement (status, relative KKT reached and its course
+over time: 1e-8 is out of reach in a benchmark's time on this LP family), the
+dominant half-step against the HBM roofline (HIP events on the library's
+stream) and a measured device-copy bandwidth; the same for the skewed LP of
+the stated size (~3e7 nonzeros); the medium LP (cache-resident) solved to
+1e-8 in FP64 and FP32; the differentiation workload; and the FP64 CPU oracle
+on a bounded sample of the headline LP.  Prints ONE JSON line.
 
-runs only the per-kernel timing of the medium LP and a 256 MiB copy of known
-size (used to calibrate hardware counters); it is the command profiled with
+    python bench.py --kernels-only --kernels-workload c3a
+
+runs only the per-half-step timing of an LP and a 256 MiB copy of known size
+(used to calibrate hardware counters); it is the command profiled with
 rocprofv3 --pmc.
 """
 import os
@@ -38,17 +47,31 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-WORKLOAD = "c2"
+HEADLINE = "c3a"
 KERNEL_SOURCES = ("paper_2507_14051_amd/csrc/kernels_iter.hip", "paper_2507_14051_amd/csrc/device.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_primal_c2.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_half_steps.md")
+C3B_GOLDEN = os.path.join(ROOT, "tests", "golden", "c3b_setup.json")
+
+WORKLOADS = {
+    "c2": "c2: m={m} n={n} nnz={nnz} (8 nonzeros per row at uniform columns, N(0,1) values, 30% equality rows, "
+          "20% free columns)",
+    "c3a": "c3a: m={m} n={n} nnz={nnz} (Zipf(1.5) row lengths capped at 50,000, {cap} rows at the cap, values "
+           "sign*10^U[-3,3], 30% equality rows, 20% free columns)",
+    "c3b": "c3b: m={m} n={n} nnz={nnz} (Zipf(1.882) row lengths capped at 50,000, {cap} rows at the cap, values "
+           "sign*10^U[-3,3], 30% equality rows, 20% free columns)",
+}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def describe(name, lp):
+    return WORKLOADS[name].format(m=lp.m, n=lp.n, nnz=lp.nnz, cap=lp.meta.get("rows_at_cap", 0))
+
+
 def algorithmic_bytes(m, n, nnz, fp=8):
-    """Bytes one kernel must move (each array once, gathered vectors once).
+    """Bytes one half-step must move (each array once, gathered vectors once).
 
     primal half-step: col_ptr 4(n+1), row idx 4 nnz, values fp nnz, y gathered fp m,
                       x, x0, c, lv, uv read (5 fp n), xbar and x written (2 fp n)
@@ -67,9 +90,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic():
-    """HBM bytes per launch of the FP64 primal half-step from the committed
-    rocprofv3 --pmc summary, if it was taken on the current kernel sources."""
+def load_traffic(workload, half):
+    """HBM bytes per launch of an FP64 half-step ("primal" or "dual") from the
+    committed rocprofv3 --pmc summary, if it was taken on the current kernel
+    sources."""
     try:
         text = open(TRAFFIC_FILE).read()
     except OSError:
@@ -80,73 +104,217 @@ def load_traffic():
     d = json.loads(m.group(1))
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return d
+    return d.get(workload, {}).get(half)
 
 
-HBM_WORKLOADS = {
-    "c3b": "c3b: m=2000000 n=5000000 nnz={nnz} Zipf(1.882) rows capped at 50,000, values +-10^U[-3,3]",
-    "c3a": "c3a: m=2000000 n=5000000 nnz={nnz} Zipf(1.5) rows capped at 50,000, values +-10^U[-3,3]",
-}
-
-
-def measure_hbm(dev, name="c3b", iters=640):
-    """Iteration rate and per-kernel GB/s on a large skewed LP (rows of
-    Zipf-distributed length) whose two matrices exceed the 256 MB Infinity
-    Cache: the HBM-bound case."""
+def copy_bandwidth(dev, nbytes=4 << 30, reps=10):
+    """Device-to-device copy of nbytes (read + write) timed with HIP events:
+    the bandwidth a plain streaming kernel reaches on this GPU."""
     import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (s.elapsed_time(e) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return round(gbs, 1)
 
+
+def kkt_course(log_, marks=(1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8), points=12):
+    """From a solve's check log: the first time each relative KKT level was
+    reached, and a dozen (seconds, iterations, rel_kkt) samples."""
+    first = {}
+    for e in log_:
+        for mk in marks:
+            if mk not in first and e["rel_kkt"] <= mk:
+                first[mk] = [round(e["seconds"], 3), e["iter"]]
+    step = max(1, len(log_) // points)
+    samples = [[round(e["seconds"], 3), e["iter"], float(f"{e['rel_kkt']:.4g}")] for e in log_[step - 1::step]]
+    if log_ and (not samples or samples[-1][1] != log_[-1]["iter"]):
+        e = log_[-1]
+        samples.append([round(e["seconds"], 3), e["iter"], float(f"{e['rel_kkt']:.4g}")])
+    return {"first_reached_s_iter": {f"{mk:g}": v for mk, v in first.items()},
+            "samples_s_iter_relkkt": samples}
+
+
+def timed_solve(prob, time_limit, **kw):
+    """One solve to 1e-8 under a time limit; status, KKT reached and its course."""
+    import torch
+    from paper_2507_14051_amd import STATUS_NAMES
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = prob.solve(tol=1e-8, time_limit_s=time_limit, want_r=False, **kw)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    info = out["info"]
+    res = {"time_limit_s": time_limit, "status": STATUS_NAMES[info["status"]], "wall_s": round(wall, 3),
+           "iters": info["iters"], "restarts": info["restarts"], "iters_per_s": round(info["iters"] / wall, 1),
+           "rel_kkt": info["rel_kkt"], "rel_gap": info["rel_gap"], "rel_primal": info["rel_primal"],
+           "rel_dual": info["rel_dual"], "omega": info["omega"],
+           "time_to_tol_s": round(wall, 3) if info["status"] == 0 else None}
+    res.update(kkt_course(out["log"]))
+    return res, out["log"]
+
+
+def half_step_roofline(prob, m, n, nnz, workload, profile_iters):
+    """The dominant FP64 half-step of an LP against the HBM roofline.  A
+    half-step is one launch unit: the transpose SpMV fused with the primal
+    update (primal), or the SpMV fused with the dual update (dual), each of
+    one or more kernels; its duration runs from the first kernel's start to
+    the last kernel's end (HIP events taking the kernels' own timestamps on
+    the library's stream, hlp_profile_iterations)."""
+    prof = prob.profile(iters=profile_iters)
+    pb, db = algorithmic_bytes(m, n, nnz)
+    half = "primal" if prof["primal_ms"] >= prof["dual_ms"] else "dual"
+    kms = prof[f"{half}_ms"]
+    kbytes = pb if half == "primal" else db
+    achieved = kbytes / (kms * 1e-3) / 1e9
+    tr = load_traffic(workload, half)
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": (tr["traffic_bytes_per_launch"] if tr else None),
+            "kernel": f"FP64 {half} half-step of {workload} "
+                      f"({'transpose SpMV fused with the primal update' if half == 'primal' else 'SpMV fused with the dual update'})",
+            "bytes_per_launch": kbytes, "avg_launch_us": round(kms * 1e3, 2),
+            "primal_avg_us": round(prof["primal_ms"] * 1e3, 2), "dual_avg_us": round(prof["dual_ms"] * 1e3, 2),
+            "primal_gbs": round(pb / (prof["primal_ms"] * 1e-3) / 1e9, 1),
+            "dual_gbs": round(db / (prof["dual_ms"] * 1e-3) / 1e9, 1),
+            "iteration_us": round(prof["iter_ms"] * 1e3, 2),
+            "iteration_gbs": round((pb + db) / (prof["iter_ms"] * 1e-3) / 1e9, 1),
+            "iteration_frac": round((pb + db) / (prof["iter_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "profiled_iterations": prof["iters"]}
+
+
+def gen(name):
     import lpgen
-    from paper_2507_14051_amd import MIXED, Problem
+    t0 = time.perf_counter()
+    lp = lpgen.config(name, seed=1,
+                      progress=lambda k, n: log(f"# {name}: rows chunk {k}/{n}") if k % 16 == 0 else None)
+    log(f"# {name}: m={lp.m} n={lp.n} nnz={lp.nnz} max_row={lp.meta['max_row']} "
+        f"rows_at_cap={lp.meta['rows_at_cap']} (generated in {time.perf_counter() - t0:.0f} s)")
+    return lp
 
+
+def measure_skewed(dev, lp, name, rate_iters, time_limit, profile_iters):
+    """Iteration rate, half-step rooflines and a time-limited solve of a large
+    skewed LP, in FP64 and in FP32 with refinement (same stepsize)."""
+    import torch
+    from paper_2507_14051_amd import MIXED, Problem
     t0 = time.perf_counter()
-    lp3 = lpgen.config(name, seed=1, progress=lambda k, n: log(f"# {name}: rows chunk {k}/{n}") if k % 8 == 0 else None)
-    gen_s = time.perf_counter() - t0
-    m3, n3, nnz3 = lp3.m, lp3.n, lp3.nnz
-    log(f"# hbm-bound {name}: m={m3} n={n3} nnz={nnz3} max_row={lp3.meta['max_row']} "
-        f"rows_at_cap={lp3.meta['rows_at_cap']} (generated in {gen_s:.0f} s)")
-    t0 = time.perf_counter()
-    p3 = Problem(lp3.A, lp3.c, lp3.lc, lp3.uc, lp3.lv, lp3.uv, device=dev)
+    p = Problem(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, device=dev)
     torch.cuda.synchronize()
-    s3 = time.perf_counter() - t0
-    panels = p3.panels()
-    dense = p3.dense()
-    _, _, _, power_iters = p3.scaling()
-    log(f"# {name}: setup {s3:.2f} s (power iterations {power_iters}), panels {panels}, dense {dense}")
-    p3.solve(max_iter=64, tol=0.0, want_r=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    p3.solve(max_iter=iters, tol=0.0, want_r=False)
-    torch.cuda.synchronize()
-    it_s = iters / (time.perf_counter() - t0)
-    pr3 = p3.profile(iters=min(100, iters))
-    pb3, db3 = algorithmic_bytes(m3, n3, nnz3)
-    hbm = {"workload": HBM_WORKLOADS[name].format(nnz=nnz3), "setup_s": round(s3, 3),
-           "power_iters": power_iters, "column_panels": panels[0], "long_rows": panels[1],
-           "narrow_panels": dense[0], "dense_rows": dense[1],
-           "iters_per_s": round(it_s, 1),
-           "primal_us": round(pr3["primal_ms"] * 1e3, 2), "dual_us": round(pr3["dual_ms"] * 1e3, 2),
-           "primal_gbs": round(pb3 / (pr3["primal_ms"] * 1e-3) / 1e9, 1),
-           "dual_gbs": round(db3 / (pr3["dual_ms"] * 1e-3) / 1e9, 1),
-           "iter_gbs": round((pb3 + db3) / (pr3["iter_ms"] * 1e-3) / 1e9, 1)}
-    hbm["iter_frac_of_peak"] = round(hbm["iter_gbs"] / HBM_PEAK_GBS, 4)
-    eta3 = p3.scaling()[2]
-    p3.close()
-    # the same plain iterations in FP32 (mixed precision: FP32 matrix copies
-    # and iterates, FP64 refinement at restarts), same stepsize
-    pm = Problem(lp3.A, lp3.c, lp3.lc, lp3.uc, lp3.lv, lp3.uv, device=dev, precision=MIXED, eta_override=eta3)
-    del lp3
-    pm.solve(max_iter=64, tol=0.0, want_r=False)
+    setup = time.perf_counter() - t0
+    _, _, eta, power_iters = p.scaling()
+    out = {"workload": describe(name, lp), "setup_s": round(setup, 3), "power_iters": power_iters,
+           "column_panels": p.panels()[0], "long_rows": p.panels()[1], "narrow_panels": p.dense()[0],
+           "dense_rows": p.dense()[1]}
+    p.solve(max_iter=64, tol=1e-8, want_r=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    pm.solve(max_iter=iters, tol=0.0, want_r=False)
+    p.solve(max_iter=rate_iters, tol=1e-8, want_r=False)
     torch.cuda.synchronize()
-    itm = iters / (time.perf_counter() - t0)
-    prm = pm.profile(iters=min(100, iters))
+    out["iters_per_s"] = round(rate_iters / (time.perf_counter() - t0), 1)
+    out["roofline"] = half_step_roofline(p, lp.m, lp.n, lp.nnz, name, profile_iters)
+    out["fp64_time_limited"], _ = timed_solve(p, time_limit)
+    log(f"# {name} fp64: {out['iters_per_s']} iter/s; {out['fp64_time_limited']['status']} "
+        f"rel_kkt {out['fp64_time_limited']['rel_kkt']:.3e}")
+    p.close()
+    del p
+    torch.cuda.empty_cache()
+    pm = Problem(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, device=dev, precision=MIXED, eta_override=eta)
+    pm.solve(max_iter=64, tol=1e-8, want_r=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pm.solve(max_iter=rate_iters, tol=1e-8, want_r=False)
+    torch.cuda.synchronize()
+    itm = rate_iters / (time.perf_counter() - t0)
+    prm = pm.profile(iters=profile_iters)
+    tl, tlog = timed_solve(pm, time_limit)
     pm.close()
-    hbm["fp32"] = {"iters_per_s": round(itm, 1), "speedup_vs_fp64": round(itm / it_s, 3),
-                   "primal_us": round(prm["primal_ms"] * 1e3, 2), "dual_us": round(prm["dual_ms"] * 1e3, 2)}
-    log(f"# hbm: {hbm}")
-    return hbm
+    del pm
+    torch.cuda.empty_cache()
+    f64 = out["fp64_time_limited"]
+    reach = next((e["seconds"] for e in tlog if e["rel_kkt"] <= f64["rel_kkt"]), None)
+    out["fp32_refined"] = {"iters_per_s": round(itm, 1), "rate_vs_fp64": round(itm / out["iters_per_s"], 3),
+                           "primal_us": round(prm["primal_ms"] * 1e3, 2), "dual_us": round(prm["dual_ms"] * 1e3, 2),
+                           "time_limited": tl,
+                           "time_to_fp64_final_kkt_s": round(reach, 3) if reach is not None else None}
+    log(f"# {name} fp32: {itm:.1f} iter/s; {tl['status']} rel_kkt {tl['rel_kkt']:.3e}")
+    return out
+
+
+def measure_c2(dev, steps, profile_iters):
+    """The medium LP, whose ~38 MB working set stays in the 256 MB Infinity
+    Cache: FP64 and FP32 solves to 1e-8 and the FP64 half-steps' rates
+    (cache-resident, not HBM-bound)."""
+    import torch
+    import lpgen
+    from paper_2507_14051_amd import MIXED, OPTIMAL, Problem
+    lp = lpgen.config("c2", seed=1)
+    p = Problem(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, device=dev)
+    p.solve(tol=1e-8, want_r=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [p.solve(tol=1e-8, want_r=False)["info"] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t64 = (time.perf_counter() - t0) / steps
+    rf = half_step_roofline(p, lp.m, lp.n, lp.nnz, "c2", profile_iters)
+    rf["bound"] = "cache-resident (38 MB per iteration, inside the 256 MB Infinity Cache): latency and L2 requests"
+    p.close()
+    pm = Problem(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, device=dev, precision=MIXED)
+    pm.solve(tol=1e-8, want_r=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mi = [pm.solve(tol=1e-8, want_r=False)["info"] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t32 = (time.perf_counter() - t0) / steps
+    pm.close()
+    out = {"workload": describe("c2", lp) + ", tol 1e-8",
+           "fp64": {"time_to_tol_s": round(t64, 4), "iters": infos[-1]["iters"], "restarts": infos[-1]["restarts"],
+                    "all_optimal": all(i["status"] == OPTIMAL for i in infos), "rel_kkt": infos[-1]["rel_kkt"],
+                    "iters_per_s": round(infos[-1]["iters"] / t64, 1)},
+           "fp32_refined": {"time_to_tol_s": round(t32, 4), "iters": mi[-1]["iters"],
+                            "all_optimal": all(i["status"] == OPTIMAL for i in mi), "rel_kkt": mi[-1]["rel_kkt"],
+                            "iters_per_s": round(mi[-1]["iters"] / t32, 1),
+                            "time_to_tol_vs_fp64": round(t64 / t32, 3)},
+           "half_steps": rf}
+    log(f"# c2: {out['fp64']} {out['fp32_refined']}")
+    return out
+
+
+def cpu_baseline(lp, name, rows_div=32, iters=64):
+    """The FP64 CPU oracle as it stands on a bounded sample of the headline LP:
+    the LP restricted to its first m/rows_div rows (rows are drawn
+    independently, so the sample keeps the row-length law; all columns and
+    their bounds kept), its own scaling (not timed), a fixed stepsize in place
+    of its power iteration (hours at this size; the stepsize does not change
+    the work per iteration), then `iters` iterations; the time per iteration
+    is scaled to the full LP by the ratio of the algorithmic bytes per
+    iteration (24 nnz + 68 n + 52 m)."""
+    import oracle
+    import lpgen
+    r = lp.m // rows_div
+    A = lp.A[:r]
+    sub = lpgen.LP(A=A, c=lp.c, lc=lp.lc[:r], uc=lp.uc[:r], lv=lp.lv, uv=lp.uv)
+    res = oracle.solve(sub.A, sub.c, sub.lc, sub.uc, sub.lv, sub.uv,
+                       oracle.Params(tol=0.0, max_iter=iters, eta_override=0.5))
+    per_iter = res.info["iter_s"] / iters
+    full = 24 * lp.nnz + 68 * lp.n + 52 * lp.m
+    part = 24 * A.nnz + 68 * lp.n + 52 * r
+    value = 1.0 / (per_iter * full / part)
+    return {"value": round(value, 4), "unit": "iter/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} oracle iterations (NumPy/SciPy FP64, one thread) on the first {r} rows of the "
+                      f"{name} LP ({A.nnz} nonzeros, all {lp.n} columns) after its own scaling "
+                      f"({res.info['setup_s']:.1f} s, not counted) with a fixed stepsize; "
+                      f"{per_iter:.3f} s per iteration scaled by the algorithmic bytes ratio {full / part:.2f} "
+                      f"to the full LP; host nproc={os.cpu_count()}"}
 
 
 def measure_adjoint(dev, K=2000, ckpt=100, reps=3):
@@ -215,11 +383,13 @@ ABLATIONS = {
 }
 
 
-def measure_ablation(dev, max_iter=600000, c1_seeds=8):
+def measure_ablation(dev, max_iter=600000, c1_seeds=8, c3b_time_limit=30.0):
     """Iterations to 1e-8 relative KKT under each switch: the medium LP (seed
     1) and the geometric mean over c1_seeds small LPs, relative to the
-    paper's settings.  One handle per LP, so every variant takes the same
-    scaling and stepsize."""
+    paper's settings; and on the skewed LP of ~3e7 nonzeros, which none of
+    the switches solves to 1e-8 in minutes, the relative KKT reached in
+    c3b_time_limit seconds.  One handle per LP, so every variant takes the
+    same scaling and stepsize."""
     import torch
 
     import lpgen
@@ -249,154 +419,145 @@ def measure_ablation(dev, max_iter=600000, c1_seeds=8):
         ratios = [r[name]["iters"] / r["paper_default"]["iters"] for r in small]
         geo[name] = {"geomean_iters_vs_default": round(math.exp(sum(map(math.log, ratios)) / len(ratios)), 3),
                      "solved": sum(r[name]["status"] == 0 for r in small), "of": len(small)}
-    return {"tol": 1e-8, "max_iter": max_iter, "c2_seed1": med, f"c1_seeds_1_to_{c1_seeds}": geo}
+    lp = gen("c3b")
+    prob = Problem(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, device=dev)
+    big = {}
+    for name, kw in ABLATIONS.items():
+        res, _ = timed_solve(prob, c3b_time_limit, **kw)
+        big[name] = {k: res[k] for k in ("status", "iters", "restarts", "rel_kkt", "rel_gap", "rel_primal",
+                                         "rel_dual", "omega", "first_reached_s_iter")}
+        log(f"# ablation c3b {name}: {big[name]}")
+    prob.close()
+    return {"tol": 1e-8, "max_iter": max_iter, "c2_seed1": med, f"c1_seeds_1_to_{c1_seeds}": geo,
+            f"c3b_full_size_{c3b_time_limit:g}s": {"workload": describe("c3b", lp), "by_switch": big}}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--step-iters", type=int, default=256,
+                    help="PDHG iterations per step (one capped FP64 solve of the headline LP)")
+    ap.add_argument("--time-limit", type=float, default=45.0,
+                    help="seconds of the time-limited headline solves (FP64 and FP32 with refinement)")
+    ap.add_argument("--time-limit-c3b", type=float, default=30.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the headline LP (no c3b, c2, adjoint)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation workload")
-    ap.add_argument("--no-hbm", action="store_true", help="skip the HBM-bound skewed LPs (c3b, c3a)")
-    ap.add_argument("--profile-iters", type=int, default=400)
+    ap.add_argument("--profile-iters", type=int, default=50)
     ap.add_argument("--kernels-only", action="store_true",
                     help="only time the half-steps of --kernels-workload and a 256 MiB copy (for counter runs)")
-    ap.add_argument("--kernels-workload", default=WORKLOAD, choices=("c2", "c3b", "c3a"))
-    ap.add_argument("--hbm-only", action="store_true", help="only the skewed-LP measurement (for profiling it)")
-    ap.add_argument("--hbm-workload", default="c3b", choices=("c3b", "c3a"),
-                    help="LP of --hbm-only (c3a: ~6.9e8 nonzeros, minutes to generate)")
+    ap.add_argument("--kernels-workload", default=HEADLINE, choices=("c2", "c3b", "c3a"))
     ap.add_argument("--ablation", action="store_true",
                     help="only the iterations-to-tolerance of the method's switches (reflection, primal weight, "
                          "restart tests)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (the build targets a single MI355X); "
+                                   "--gpus must be 1"}))
         sys.exit(2)
 
     import torch
 
-    import lpgen
-    from paper_2507_14051_amd import MIXED, OPTIMAL, Problem
+    from paper_2507_14051_amd import MIXED, Problem
 
     dev = torch.device("cuda:0")
     if args.ablation:
         print(json.dumps({"ablation": measure_ablation(dev)}), flush=True)
         return
-    if args.hbm_only:
-        iters = 640 if args.hbm_workload == "c3b" else 128
-        print(json.dumps({"hbm_only": True, "hbm_bound": measure_hbm(dev, args.hbm_workload, iters)}), flush=True)
+    if args.kernels_only:
+        lp = gen(args.kernels_workload)
+        prob = Problem(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, device=dev)
+        prof = prob.profile(iters=args.profile_iters)
+        pb, db = algorithmic_bytes(lp.m, lp.n, lp.nnz)
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)   # 256 MiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"kernels_only": True, "workload": args.kernels_workload,
+                          "primal_us": prof["primal_ms"] * 1e3, "dual_us": prof["dual_ms"] * 1e3,
+                          "iters": prof["iters"], "primal_bytes": pb, "dual_bytes": db,
+                          "copy_bytes": 2 * a.numel() * 8, "kernel_source_hash": kernel_source_hash()}), flush=True)
+        prob.close()
         return
-    wl = args.kernels_workload if args.kernels_only else WORKLOAD
-    lp = lpgen.config(wl, seed=1)
-    tol = lpgen.tolerance(wl)
-    m, n, nnz = lp.m, lp.n, lp.nnz
-    pb, db = algorithmic_bytes(m, n, nnz)
-    log(f"# workload {wl}: m={m} n={n} nnz={nnz} max_row={lp.meta['max_row']}")
 
+    # ---------------------------------------------------------------- headline
+    lp = gen(HEADLINE)
+    m, n, nnz = lp.m, lp.n, lp.nnz
+    workload = describe(HEADLINE, lp)
     t0 = time.perf_counter()
     prob = Problem(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, device=dev)
     torch.cuda.synchronize()
     setup_wall = time.perf_counter() - t0
     _, _, eta, power_iters = prob.scaling()
-
-    if args.kernels_only:
-        prof = prob.profile(iters=args.profile_iters)
-        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)   # 256 MiB
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"kernels_only": True, "workload": wl, "primal_us": prof["primal_ms"] * 1e3,
-                          "dual_us": prof["dual_ms"] * 1e3, "iters": prof["iters"],
-                          "primal_bytes": pb, "dual_bytes": db, "copy_bytes": 2 * a.numel() * 8,
-                          "kernel_source_hash": kernel_source_hash()}), flush=True)
-        prob.close()
-        return
-
+    log(f"# {HEADLINE}: setup {setup_wall:.2f} s (power iterations {power_iters}), panels {prob.panels()}, "
+        f"dense {prob.dense()}")
     for _ in range(args.warmup):
-        prob.solve(tol=tol, want_r=False)
+        prob.solve(tol=1e-8, max_iter=args.step_iters, want_r=False)
     torch.cuda.synchronize()
     infos = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        infos.append(prob.solve(tol=tol, want_r=False)["info"])
+        infos.append(prob.solve(tol=1e-8, max_iter=args.step_iters, want_r=False)["info"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     iters = sum(i["iters"] for i in infos)
-    ok = all(i["status"] == OPTIMAL for i in infos)
     ms_per_step = 1e3 * elapsed / args.steps
-    log(f"# fp64: {infos[-1]['iters']} iters, {ms_per_step:.1f} ms/solve, rel_kkt {infos[-1]['rel_kkt']:.2e}")
-
-    # dominant kernel against the roofline: HIP events around every launch
-    prof = prob.profile(iters=args.profile_iters)
-    kern = "primal" if prof["primal_ms"] >= prof["dual_ms"] else "dual"
-    kms = prof["primal_ms"] if kern == "primal" else prof["dual_ms"]
-    kbytes = pb if kern == "primal" else db
-    achieved = kbytes / (kms * 1e-3) / 1e9
-    tr = load_traffic() if kern == "primal" else None
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": (tr["traffic_bytes_per_launch"] if tr else None),
-                "kernel": f"k_{kern} (fused {'transpose ' if kern == 'primal' else ''}SpMV + update), FP64",
-                "bytes_per_launch": kbytes, "avg_launch_us": round(kms * 1e3, 3),
-                "primal_avg_launch_us": round(prof["primal_ms"] * 1e3, 3),
-                "dual_avg_launch_us": round(prof["dual_ms"] * 1e3, 3),
-                "iter_us_with_events": round(prof["iter_ms"] * 1e3, 3),
-                "solve_iter_us": round(1e6 * elapsed / iters, 3)}
+    log(f"# {HEADLINE} steps: {iters / elapsed:.1f} iter/s, {ms_per_step:.1f} ms per step")
+    roofline = half_step_roofline(prob, m, n, nnz, HEADLINE, args.profile_iters)
+    fp64_tl, _ = timed_solve(prob, args.time_limit)
+    log(f"# {HEADLINE} fp64 time-limited: {fp64_tl['status']} rel_kkt {fp64_tl['rel_kkt']:.3e}")
     prob.close()
-
-    mixed = None
-    if not args.no_mixed:
-        probm = Problem(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, device=dev, precision=MIXED)
-        probm.solve(tol=tol, want_r=False)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        mi = [probm.solve(tol=tol, want_r=False)["info"] for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        mt = (time.perf_counter() - t0) / args.steps
-        profm = probm.profile(iters=args.profile_iters)
-        pb32, db32 = algorithmic_bytes(m, n, nnz, fp=4)
-        mixed = {"time_to_tol_s": round(mt, 4), "iters": mi[-1]["iters"], "status": mi[-1]["status"],
-                 "rel_kkt": mi[-1]["rel_kkt"], "iters_per_s": round(mi[-1]["iters"] / mt, 1),
-                 "speedup_vs_fp64_time": round((elapsed / args.steps) / mt, 3),
-                 "primal_us": round(profm["primal_ms"] * 1e3, 3), "dual_us": round(profm["dual_ms"] * 1e3, 3),
-                 "primal_gbs": round(pb32 / (profm["primal_ms"] * 1e-3) / 1e9, 1)}
-        probm.close()
-        log(f"# mixed: {mixed}")
-
-    hbm = hbm_a = None
-    if not args.no_hbm:
-        hbm = measure_hbm(dev, "c3b", 640)
-        hbm_a = measure_hbm(dev, "c3a", 128)
-
-    adjoint = None if args.no_adjoint else measure_adjoint(dev)
+    del prob
+    torch.cuda.empty_cache()
+    pm = Problem(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, device=dev, precision=MIXED, eta_override=eta)
+    pm.solve(max_iter=64, tol=1e-8, want_r=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pm.solve(max_iter=args.step_iters, tol=1e-8, want_r=False)
+    torch.cuda.synchronize()
+    rate32 = args.step_iters / (time.perf_counter() - t0)
+    fp32_tl, f32log = timed_solve(pm, args.time_limit)
+    pm.close()
+    del pm
+    torch.cuda.empty_cache()
+    reach = next((e["seconds"] for e in f32log if e["rel_kkt"] <= fp64_tl["rel_kkt"]), None)
+    mixed = {"iters_per_s": round(rate32, 1), "rate_vs_fp64": round(rate32 / (iters / elapsed), 3),
+             "time_limited": fp32_tl,
+             "time_to_fp64_final_kkt_s": round(reach, 3) if reach is not None else None}
+    log(f"# {HEADLINE} fp32 time-limited: {fp32_tl['status']} rel_kkt {fp32_tl['rel_kkt']:.3e}")
+    copy_gbs = copy_bandwidth(dev)
+    roofline["copy_peak_gbs"] = copy_gbs
+    roofline["frac_of_copy_peak"] = round(roofline["achieved"] / copy_gbs, 4)
 
     cpu = None
     if not args.no_cpu:
-        import oracle
-        K = 2000
-        res = oracle.solve(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, oracle.Params(tol=tol, max_iter=K))
-        cpu = {"value": round(K / res.info["iter_s"], 3), "unit": "iter/s", "cores": 1, "kind": "oracle",
-               "sample": f"{K} oracle iterations of the same LP (its own scaling and power iteration, "
-                         f"{res.info['setup_s']:.1f} s, not counted), NumPy/SciPy FP64 single thread; "
-                         f"host nproc={os.cpu_count()}"}
+        cpu = cpu_baseline(lp, HEADLINE)
         log(f"# cpu: {cpu}")
+    del lp
+
+    extra = {}
+    if not args.no_extra:
+        extra["c3b"] = measure_skewed(dev, gen("c3b"), "c3b", 640, args.time_limit_c3b, args.profile_iters)
+        extra["c2_cache_resident"] = measure_c2(dev, 2, 400)
+        if not args.no_adjoint:
+            extra["adjoint"] = measure_adjoint(dev)
 
     line = {
-        "metric": "PDHG iterations/s, FP64 solve to 1e-8 relative KKT (time-to-tolerance and HBM roofline alongside)",
-        "value": round(iters / elapsed, 1), "unit": "iter/s", "n_gpus": 1, "steps": args.steps,
+        "metric": "PDHG iterations/s of FP64 restarted Halpern PDHG (time to 1e-8 relative KKT, FP32-vs-FP64 and "
+                  "the HBM roofline alongside)",
+        "value": round(iters / elapsed, 2), "unit": "iter/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{WORKLOAD}: m={m} n={n} nnz={nnz} (8/row uniform columns, N(0,1) values, "
-                               f"30% equality rows, 20% free columns), tol {tol:g}",
+        "config": {"workload": workload,
+                   "step": f"one FP64 solve from the all-zero start, paper settings, tol 1e-8, capped at "
+                           f"{args.step_iters} iterations (a check every 64)",
                    "seed": 1, "global_batch": 1, "parallelism": "single GPU"},
-        "time_to_tol_s": round(elapsed / args.steps, 4), "iters_per_solve": infos[-1]["iters"],
-        "restarts": infos[-1]["restarts"], "rel_kkt": infos[-1]["rel_kkt"], "all_optimal": ok,
-        "setup_s": round(setup_wall, 4), "power_iters": power_iters,
-        "mixed": mixed, "hbm_bound": hbm, "hbm_bound_c3a": hbm_a, "adjoint": adjoint, "roofline": roofline,
-        "cpu_baseline": cpu,
+        "setup_s": round(setup_wall, 3), "power_iters": power_iters, "eta": eta,
+        "time_to_tol_s": fp64_tl["time_to_tol_s"], "fp64_time_limited": fp64_tl, "mixed": mixed,
+        "roofline": roofline, "cpu_baseline": cpu, **extra,
     }
     print(json.dumps(line), flush=True)
 

@@ -142,6 +142,21 @@ typedef struct {
   double setup_s, solve_s; /* wall seconds in hlp_lp_create / hlp_solve */
 } hlp_info;
 
+/* One restart/termination test of a solve (Sec. 3, "Adaptive restart";
+ * Sec. 4).  Values refer to the state the test saw. */
+typedef struct {
+  int64_t iter;            /* T: PDHG iterations done when the test ran */
+  int64_t k;               /* k: iterations of the current epoch, counted after the increment */
+  double r;                /* fixed-point residual ||z - PDHG(z)||_P at this iteration */
+  double r0;               /* the epoch's r(z^{n,0}), measured at its first iteration */
+  double rel_kkt, rel_gap, rel_primal, rel_dual;  /* of the PDHG output zhat, original LP */
+  double omega;            /* primal weight in force during the iterations before the test
+                              (before the PID update that a restart here applies) */
+  double seconds;          /* wall seconds since hlp_solve began */
+  int32_t restart;         /* 1: the test restarted (anchor reset, PID update) */
+  int32_t reserved;        /* 0 */
+} hlp_check;
+
 /* Fill *p with the defaults above.  Errors: HLP_EINVAL if p is NULL. */
 hlp_err hlp_params_default(hlp_params* p);
 
@@ -211,6 +226,16 @@ hlp_err hlp_lp_update_vectors(hlp_lp* lp, const double* c, const double* lc,
  */
 hlp_err hlp_solve(hlp_lp* lp, const hlp_params* p, const double* x0, const double* y0,
                   double* x, double* y, double* r, hlp_info* info, double* trace);
+
+/*
+ * The check log of the last hlp_solve on this handle: one hlp_check per
+ * restart/termination test, in order (kept in host memory by the handle,
+ * replaced by the next hlp_solve).  Writes the number of records to *count
+ * (host, required) and copies the first min(cap, *count) of them to out (host
+ * array, may be NULL with cap = 0 to query the count).
+ * Errors: HLP_EINVAL for a NULL handle or count, cap < 0, or out NULL with cap > 0.
+ */
+hlp_err hlp_check_log(const hlp_lp* lp, hlp_check* out, int64_t cap, int64_t* count);
 
 /* Copy the scaling diagonals (device double[m], double[n]; either may be NULL)
  * and return eta and the power iterations through the host pointers (may be NULL). */

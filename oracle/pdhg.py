@@ -77,6 +77,7 @@ class Params:
     restart_to_current: int = 0     # 0: new anchor = PDHG(z); 1: the Halpern iterate z
     pid_min_norm: float = 1e-10
     trace_iters: int = 0
+    trace_at: tuple = ()            # further iterations t whose (xhat, yhat, x, y) are kept in trace["at"][t]
 
 
 @dataclass
@@ -291,6 +292,8 @@ def solve(A, c, lc, uc, lv, uv, params: Params | None = None, x0=None, y0=None):
     if p.trace_iters > 0:
         T = p.trace_iters
         trace = dict(xh=np.zeros((T, n)), yh=np.zeros((T, m)), x=np.zeros((T, n)), y=np.zeros((T, m)))
+    if p.trace_at:
+        trace["at"] = {}
     log = []
 
     while True:
@@ -313,13 +316,16 @@ def solve(A, c, lc, uc, lv, uv, params: Params | None = None, x0=None, y0=None):
             trace["yh"][t - 1] = yh
             trace["x"][t - 1] = x
             trace["y"][t - 1] = y
+        if t in p.trace_at:
+            trace["at"][t] = (xh.copy(), yh.copy(), x.copy(), y.copy())
         if not check:
             continue
 
         xu = dc * xh
         yu = dr * yh
         kk = _kkt(A, c, lc, uc, lv, uv, xu, yu)
-        entry = dict(t=t, k=k, r=r, r0=r0, rel_kkt=kk["rel_kkt"], omega=omega, restart=False)
+        entry = dict(t=t, k=k, r=r, r0=r0, rel_kkt=kk["rel_kkt"], rel_gap=kk["rel_gap"],
+                     rel_primal=kk["rel_primal"], rel_dual=kk["rel_dual"], omega=omega, restart=False)
         log.append(entry)
         status = None
         if not all(math.isfinite(v) for v in (kk["pobj"], kk["dobj"], kk["rho_p"], kk["rho_d"], r)):

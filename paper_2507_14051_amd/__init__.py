@@ -13,7 +13,7 @@ from __future__ import annotations
 import numpy as np
 
 from .hlp import (FP64, MIXED, HLP_OK, ITER_LIMIT, NUMERICAL, OPTIMAL, STATUS_NAMES, SYMBOLS, TIME_LIMIT,
-                  HlpError, HlpInfo, HlpParams, hlp_last_error, hlp_lp_create, hlp_lp_destroy,
+                  HlpCheck, HlpError, HlpInfo, HlpParams, hlp_check_log, hlp_last_error, hlp_lp_create, hlp_lp_destroy,
                   hlp_lp_panels, hlp_lp_scaling, hlp_lp_transpose, hlp_lp_update_vectors, hlp_params_default,
                   hlp_profile_iterations, hlp_solve, hlp_tape_bytes, hlp_unrolled_backward,
                   hlp_unrolled_forward, hlp_workspace_bytes, lib)
@@ -92,7 +92,8 @@ class Problem:
         hlp_lp_update_vectors(self.handle, *self.vectors)
 
     def solve(self, x0=None, y0=None, trace_iters=0, want_r=True, **params):
-        """Run hlp_solve; returns dict(x, y, r, info, trace) with torch tensors."""
+        """Run hlp_solve; returns dict(x, y, r, info, log, trace): torch tensors, the
+        info dict and the check log (hlp_check_log, a list of dicts)."""
         import torch
         p = self.params_for(trace_iters=trace_iters, **params)
         f64 = dict(dtype=torch.float64, device=self.device)
@@ -103,7 +104,7 @@ class Problem:
         x0 = None if x0 is None else _dev_tensor(x0, torch.float64, self.device)
         y0 = None if y0 is None else _dev_tensor(y0, torch.float64, self.device)
         info = hlp_solve(self.handle, p, x0, y0, x, y, r, trace)
-        out = dict(x=x, y=y, r=r, info=info.as_dict())
+        out = dict(x=x, y=y, r=r, info=info.as_dict(), log=hlp_check_log(self.handle))
         if trace is not None:
             T = trace.view(trace_iters, 2 * self.n + 2 * self.m)
             n, m = self.n, self.m

@@ -236,6 +236,18 @@ hlp_err run_loop(hlp_lp* lp, const hlp_params& p, const double* x0, const double
     const double r = fixed_point_residual(RC, eta, om);
     if (rs.first_res) c.r0 = rs.len == 1 ? r : fixed_point_residual(R + SLOT_R0 * NQ, eta, om);
     kk = kkt_from(RC, lp);
+    hlp_check rec{};
+    rec.iter = c.t;
+    rec.k = c.k;
+    rec.r = r;
+    rec.r0 = c.r0;
+    rec.rel_kkt = kk.rel;
+    rec.rel_gap = kk.rel_gap;
+    rec.rel_primal = kk.rel_p;
+    rec.rel_dual = kk.rel_d;
+    rec.omega = c.omega;
+    rec.seconds = now_s() - t_start;
+    lp->check_log.push_back(rec);
     status = -1;
     if (!kk.finite || !std::isfinite(r)) status = HLP_NUMERICAL;
     else if (kk.rel <= p.tol) status = HLP_OPTIMAL;
@@ -243,6 +255,7 @@ hlp_err run_loop(hlp_lp* lp, const hlp_params& p, const double* x0, const double
     else if (now_s() - t_start >= p.time_limit_s) status = HLP_TIME_LIMIT;
     if (status >= 0) return HLP_OK;
     if (restart_test(r, c.r0, c.r_prev, c.k, c.t, p)) {
+      lp->check_log.back().restart = 1;
       ++c.restarts;
       const double om_new = pid_update(om, std::sqrt(RC[Q_XA2]), std::sqrt(RC[Q_YA2]), c, p);
       if (mixed) {
@@ -290,6 +303,7 @@ hlp_err hlp_solve(hlp_lp* lp, const hlp_params* pp, const double* x0, const doub
     return HLP_EUNSUPPORTED;
   }
   const double t0 = now_s();
+  lp->check_log.clear();
   Ctl c;
   Kkt kk{};
   int32_t status = -1;
@@ -315,6 +329,18 @@ hlp_err hlp_solve(hlp_lp* lp, const hlp_params* pp, const double* x0, const doub
     info->setup_s = lp->setup_s;
     info->solve_s = now_s() - t0;
   }
+  return HLP_OK;
+}
+
+hlp_err hlp_check_log(const hlp_lp* lp, hlp_check* out, int64_t cap, int64_t* count) {
+  if (!lp || !count || cap < 0 || (!out && cap > 0)) {
+    set_error("hlp_check_log: NULL handle or count, cap < 0, or NULL out with cap > 0");
+    return HLP_EINVAL;
+  }
+  const int64_t total = (int64_t)lp->check_log.size();
+  *count = total;
+  const int64_t k = std::min(cap, total);
+  for (int64_t i = 0; i < k; ++i) out[i] = lp->check_log[(size_t)i];
   return HLP_OK;
 }
 

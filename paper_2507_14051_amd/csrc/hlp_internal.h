@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/hlp.h"
 
@@ -169,6 +170,8 @@ struct hlp_lp {
   double* pu = nullptr;
   double* pw = nullptr;
   double setup_s = 0.0;
+  // one record per check of the last hlp_solve (host memory)
+  std::vector<hlp_check> check_log;
 };
 
 namespace hlp {

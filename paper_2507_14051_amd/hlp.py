@@ -19,7 +19,7 @@ STATUS_NAMES = {OPTIMAL: "OPTIMAL", ITER_LIMIT: "ITER_LIMIT", TIME_LIMIT: "TIME_
 
 # The exported symbols, in the order of include/hlp.h.
 SYMBOLS = ("hlp_params_default", "hlp_workspace_bytes", "hlp_lp_create", "hlp_lp_update_vectors",
-           "hlp_solve", "hlp_lp_scaling", "hlp_lp_transpose", "hlp_lp_panels", "hlp_tape_bytes", "hlp_unrolled_forward",
+           "hlp_solve", "hlp_check_log", "hlp_lp_scaling", "hlp_lp_transpose", "hlp_lp_panels", "hlp_tape_bytes", "hlp_unrolled_forward",
            "hlp_unrolled_backward", "hlp_profile_iterations", "hlp_lp_destroy", "hlp_last_error")
 
 
@@ -50,6 +50,17 @@ class HlpInfo(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class HlpCheck(C.Structure):
+    _fields_ = [
+        ("iter", C.c_int64), ("k", C.c_int64), ("r", C.c_double), ("r0", C.c_double),
+        ("rel_kkt", C.c_double), ("rel_gap", C.c_double), ("rel_primal", C.c_double), ("rel_dual", C.c_double),
+        ("omega", C.c_double), ("seconds", C.c_double), ("restart", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
 class HlpError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"hlp error {code}: {msg}")
@@ -73,6 +84,7 @@ def lib():
         L.hlp_lp_create.argtypes = [I32, I32, I64] + [P] * 8 + [C.POINTER(HlpParams), P, SZ, P, C.POINTER(P)]
         L.hlp_lp_update_vectors.argtypes = [P] * 6
         L.hlp_solve.argtypes = [P, C.POINTER(HlpParams), P, P, P, P, P, C.POINTER(HlpInfo), P]
+        L.hlp_check_log.argtypes = [P, C.POINTER(HlpCheck), I64, C.POINTER(I64)]
         L.hlp_lp_scaling.argtypes = [P, P, P, C.POINTER(C.c_double), C.POINTER(I32)]
         L.hlp_lp_transpose.argtypes = [P, P, P, P]
         L.hlp_lp_panels.argtypes = [P] + [C.POINTER(I32)] * 4
@@ -144,6 +156,15 @@ def hlp_solve(lp, params, x0=None, y0=None, x=None, y=None, r=None, trace=None) 
     _check(lib().hlp_solve(lp, C.byref(params) if params is not None else None, _ptr(x0), _ptr(y0), _ptr(x),
                            _ptr(y), _ptr(r), C.byref(info), _ptr(trace)))
     return info
+
+
+def hlp_check_log(lp) -> list:
+    """The check log of the last hlp_solve on lp, as a list of dicts."""
+    count = C.c_int64(0)
+    _check(lib().hlp_check_log(lp, None, 0, C.byref(count)))
+    buf = (HlpCheck * max(count.value, 1))()
+    _check(lib().hlp_check_log(lp, buf, count.value, C.byref(count)))
+    return [buf[i].as_dict() for i in range(count.value)]
 
 
 def hlp_lp_scaling(lp, d_r=None, d_c=None):

@@ -44,11 +44,11 @@ def _c_layout(tmp_path, struct, fields):
     return {k: int(v) for k, v in (ln.split() for ln in out.strip().splitlines())}
 
 
-@pytest.mark.parametrize("name", ["HlpParams", "HlpInfo"])
+@pytest.mark.parametrize("name", ["HlpParams", "HlpInfo", "HlpCheck"])
 def test_struct_layout_matches_header(tmp_path, name):
     from paper_2507_14051_amd import hlp
     cls = getattr(hlp, name)
-    cname = {"HlpParams": "hlp_params", "HlpInfo": "hlp_info"}[name]
+    cname = {"HlpParams": "hlp_params", "HlpInfo": "hlp_info", "HlpCheck": "hlp_check"}[name]
     fields = [f for f, _ in cls._fields_]
     lay = _c_layout(tmp_path, cname, fields)
     assert lay["size"] == C.sizeof(cls)

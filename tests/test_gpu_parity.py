@@ -268,29 +268,6 @@ def test_graph_replay_c2_partial_run():
     prob.close()
 
 
-@pytest.mark.timeout(600)
-def test_c3b_full_size_first_iterations_match_oracle():
-    """The large skewed LP at its full size (m=2e6, n=5e6, 29.6M nonzeros) in
-    the bench's configuration (column panels, dense rows): scaling diagonals
-    and the end point after 3 iterations (a check, a plain iteration, a check)
-    against the oracle.  Both sides take the same given stepsize, so the
-    oracle's power iteration (minutes at this size) is not needed."""
-    lp = lpgen.config("c3b", seed=1)
-    announce(f"c3b full size vs oracle nnz={lp.nnz}")
-    eta = 1e-3
-    prob = problem(lp, eta=eta)
-    assert prob.panels()[0] == 24 and prob.dense()[1] > 0
-    dr, dc, _, _ = prob.scaling()
-    out = np_out(prob.solve(tol=0.0, max_iter=3))
-    prob.close()
-    At, dr0, dc0 = rescale(lp.A, 10, 1)
-    assert rel(dr.cpu().numpy(), dr0) <= 1e-12 and rel(dc.cpu().numpy(), dc0) <= 1e-12
-    ref = oracle.solve(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, Params(tol=0.0, max_iter=3, eta_override=eta))
-    ex, ey = rel(out["x"], ref.x), rel(out["y"], ref.y)
-    print(f"c3b 3 iterations vs oracle: x {ex:.1e} y {ey:.1e}")
-    assert ex <= TRAJ_TOL and ey <= TRAJ_TOL
-
-
 # Switches of the method the paper argues for (Sec. 3): the reflection gamma,
 # the primal-weight rule and each of the three restart conditions.  PID gains
 # (theta, 0, 0) are the exponentially smoothed distance-ratio update the paper
@@ -328,3 +305,29 @@ def test_ablation_settings_match_oracle(name):
     if name == "no_restarts":
         assert info["restarts"] == 0 and info["omega"] == 1.0
     print(f"{name}: {info['iters']} iterations, {info['restarts']} restarts, worst trajectory error {worst:.1e}")
+
+
+@pytest.mark.parametrize("name", ["paper_default"] + sorted(ABLATIONS))
+def test_ablation_settings_match_oracle_on_scaled_c3b(name):
+    """The switches on the skewed family (the c3b recipe scaled to m=4,000,
+    n=10,000: Zipf(1.882) rows, log-uniform values), where the primal-weight
+    rule decides how far the method gets: the first 100 iterates, then 3,000
+    iterations through several restarts with the same check log (iterations,
+    restart decisions, primal weights, residuals), end point and KKT error as
+    the oracle."""
+    lp = lpgen.config("c3b", seed=1, scale=0.002)
+    announce(f"ablation {name} on scaled c3b nnz={lp.nnz}")
+    kw = ABLATIONS.get(name, {})
+    out, ref, worst = _trajectory_case(lp, T=100, tol=1e-8, max_iter=3000, **kw)
+    info = out["info"]
+    assert info["status"] == ref.status and info["iters"] == ref.iters and info["restarts"] == ref.restarts
+    glog = out["log"]
+    assert [e["iter"] for e in glog] == [e["t"] for e in ref.log]
+    assert [bool(e["restart"]) for e in glog] == [e["restart"] for e in ref.log]
+    for g, o in zip(glog, ref.log):
+        assert g["omega"] == pytest.approx(o["omega"], rel=1e-9)
+        assert g["r"] == pytest.approx(o["r"], rel=1e-7)
+        assert g["rel_kkt"] == pytest.approx(o["rel_kkt"], rel=1e-6)
+    assert rel(out["x"].cpu().numpy(), ref.x) <= 1e-8 and rel(out["y"].cpu().numpy(), ref.y) <= 1e-8
+    print(f"{name} scaled c3b: {info['iters']} iterations, {info['restarts']} restarts, omega {info['omega']:.3g}, "
+          f"rel_kkt {info['rel_kkt']:.2e}, worst trajectory error {worst:.1e}")
