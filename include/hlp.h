@@ -301,6 +301,34 @@ hlp_err hlp_unrolled_backward(hlp_lp* lp, const void* tape, size_t tape_bytes,
  */
 hlp_err hlp_profile_iterations(hlp_lp* lp, const hlp_params* p, int32_t iters, double* ms_out);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): hlp_lp_create
+ * followed by hlp_solve in one call, with the library's own static device
+ * scratch as the workspace.  It allocates no device memory and calls no
+ * allocating HIP or torch routine; HIP graphs are not used (p->graphs is
+ * ignored), no trace is recorded and no check log is kept.
+ *
+ *   m, n, nnz, row_ptr, col_idx, val, c, lc, uc, lv, uv   as hlp_lp_create (device)
+ *   p            host, NULL = defaults ([setup] fields and solve fields both apply)
+ *   hip_stream   hipStream_t for all work (NULL = default stream)
+ *   x, y, r, info  outputs as hlp_solve (device double[n], [m], [n]; host info; any may be NULL)
+ *
+ * The scratch is a file-scope device array of HLP_STATIC_SCRATCH_BYTES (160 MiB):
+ * each GPU the library runs on holds its own copy until the process ends, and
+ * every call on a GPU uses that GPU's copy, so calls that overlap on one GPU
+ * (from several threads or streams) race and must be serialised by the caller.
+ * An LP whose workspace (hlp_workspace_bytes with *p) exceeds it gets
+ * HLP_ENOMEM before any device work.  Results are bitwise those of
+ * hlp_lp_create + hlp_solve with graphs off.
+ * Errors: as hlp_lp_create and hlp_solve; HLP_ENOMEM when the LP does not fit.
+ */
+#define HLP_STATIC_SCRATCH_BYTES ((size_t)160 << 20)
+hlp_err hlp_solve_static(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                         const double* val, const double* c, const double* lc, const double* uc,
+                         const double* lv, const double* uv, const hlp_params* p, void* hip_stream,
+                         double* x, double* y, double* r, hlp_info* info);
+
 /* Destroy a handle (does not touch the workspace).  NULL is ignored. */
 void hlp_lp_destroy(hlp_lp* lp);
 

@@ -485,15 +485,18 @@ static hlp_err validate_and_scale_vectors(hlp_lp* lp, const double* c, const dou
   return HLP_OK;
 }
 
-hlp_err hlp_lp_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
-                      const double* val, const double* c, const double* lc, const double* uc,
-                      const double* lv, const double* uv, const hlp_params* p, void* workspace,
-                      size_t workspace_bytes, void* hip_stream, hlp_lp** out) {
-  if (!out) {
-    set_error("hlp_lp_create: NULL out");
-    return HLP_EINVAL;
-  }
-  *out = nullptr;
+}  // extern "C"
+
+namespace hlp {
+
+// Setup of hlp_lp_create into a handle object the caller provides (a fresh
+// hlp_lp): argument checks, workspace layout, validation, copy, transpose,
+// rescaling, panel layout, scaled vectors and the stepsize.  On error the
+// object may hold pointers into the workspace and must be discarded.
+hlp_err setup_into(hlp_lp* lp, int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                   const double* val, const double* c, const double* lc, const double* uc, const double* lv,
+                   const double* uv, const hlp_params* p, void* workspace, size_t workspace_bytes,
+                   void* hip_stream) {
   HLP_TRY(check_sizes(m, n, nnz));
   if (!row_ptr || (nnz > 0 && (!col_idx || !val)) || !workspace) {
     set_error("hlp_lp_create: NULL input pointer");
@@ -526,11 +529,6 @@ hlp_err hlp_lp_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr,
     set_error("workspace too small: need " + std::to_string(need) + " bytes");
     return HLP_ENOMEM;
   }
-  hlp_lp* lp = new (std::nothrow) hlp_lp();
-  if (!lp) {
-    set_error("out of host memory");
-    return HLP_ENOMEM;
-  }
   const double t0 = now_s();
   lp->m = m;
   lp->n = n;
@@ -538,10 +536,7 @@ hlp_err hlp_lp_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr,
   lp->stream = reinterpret_cast<hipStream_t>(hip_stream);
   lp->precision = p->precision;
   carve(lp, workspace, m, n, nnz, p->precision, P, p->panel_row_min, p->dense_row_min);
-  auto fail = [&](hlp_err e) {
-    delete lp;
-    return e;
-  };
+  auto fail = [](hlp_err e) { return e; };
   // 1. row pointers, then the rows themselves
   if (hipError_t e = launch_fill(reinterpret_cast<double*>(lp->flags), 0.0, 1, lp->stream); e != hipSuccess)
     return fail(hip_fail(e, "fill"));
@@ -612,6 +607,33 @@ hlp_err hlp_lp_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr,
   }
   if (hipError_t e = hipStreamSynchronize(lp->stream); e != hipSuccess) return fail(hip_fail(e, "sync"));
   lp->setup_s = now_s() - t0;
+  return HLP_OK;
+}
+
+}  // namespace hlp
+
+extern "C" {
+
+hlp_err hlp_lp_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                      const double* val, const double* c, const double* lc, const double* uc,
+                      const double* lv, const double* uv, const hlp_params* p, void* workspace,
+                      size_t workspace_bytes, void* hip_stream, hlp_lp** out) {
+  if (!out) {
+    set_error("hlp_lp_create: NULL out");
+    return HLP_EINVAL;
+  }
+  *out = nullptr;
+  hlp_lp* lp = new (std::nothrow) hlp_lp();
+  if (!lp) {
+    set_error("out of host memory");
+    return HLP_ENOMEM;
+  }
+  const hlp_err e = setup_into(lp, m, n, nnz, row_ptr, col_idx, val, c, lc, uc, lv, uv, p, workspace,
+                               workspace_bytes, hip_stream);
+  if (e != HLP_OK) {
+    delete lp;
+    return e;
+  }
   *out = lp;
   return HLP_OK;
 }

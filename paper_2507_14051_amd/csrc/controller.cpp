@@ -247,7 +247,7 @@ hlp_err run_loop(hlp_lp* lp, const hlp_params& p, const double* x0, const double
     rec.rel_dual = kk.rel_d;
     rec.omega = c.omega;
     rec.seconds = now_s() - t_start;
-    lp->check_log.push_back(rec);
+    if (lp->keep_log) lp->check_log.push_back(rec);
     status = -1;
     if (!kk.finite || !std::isfinite(r)) status = HLP_NUMERICAL;
     else if (kk.rel <= p.tol) status = HLP_OPTIMAL;
@@ -255,7 +255,7 @@ hlp_err run_loop(hlp_lp* lp, const hlp_params& p, const double* x0, const double
     else if (now_s() - t_start >= p.time_limit_s) status = HLP_TIME_LIMIT;
     if (status >= 0) return HLP_OK;
     if (restart_test(r, c.r0, c.r_prev, c.k, c.t, p)) {
-      lp->check_log.back().restart = 1;
+      if (lp->keep_log) lp->check_log.back().restart = 1;
       ++c.restarts;
       const double om_new = pid_update(om, std::sqrt(RC[Q_XA2]), std::sqrt(RC[Q_YA2]), c, p);
       if (mixed) {

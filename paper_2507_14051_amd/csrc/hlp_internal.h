@@ -170,8 +170,10 @@ struct hlp_lp {
   double* pu = nullptr;
   double* pw = nullptr;
   double setup_s = 0.0;
-  // one record per check of the last hlp_solve (host memory)
+  // one record per check of the last hlp_solve (host memory); not kept when
+  // keep_log is false (the allocation-free entry point)
   std::vector<hlp_check> check_log;
+  bool keep_log = true;
 };
 
 namespace hlp {
@@ -189,6 +191,13 @@ hlp_err hip_fail(hipError_t e, const char* what);
     hlp_err r_ = (call);                \
     if (r_ != HLP_OK) return r_;        \
   } while (0)
+
+// ---------------------------------------------------------------- setup
+// hlp_lp_create's work into a fresh handle object owned by the caller.
+hlp_err setup_into(hlp_lp* lp, int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                   const double* val, const double* c, const double* lc, const double* uc, const double* lv,
+                   const double* uv, const hlp_params* p, void* workspace, size_t workspace_bytes,
+                   void* hip_stream);
 
 // ---------------------------------------------------------------- layout
 // Carve the workspace.  With lp->... == nullptr base, only computes the size.

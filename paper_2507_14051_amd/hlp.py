@@ -20,7 +20,8 @@ STATUS_NAMES = {OPTIMAL: "OPTIMAL", ITER_LIMIT: "ITER_LIMIT", TIME_LIMIT: "TIME_
 # The exported symbols, in the order of include/hlp.h.
 SYMBOLS = ("hlp_params_default", "hlp_workspace_bytes", "hlp_lp_create", "hlp_lp_update_vectors",
            "hlp_solve", "hlp_check_log", "hlp_lp_scaling", "hlp_lp_transpose", "hlp_lp_panels", "hlp_tape_bytes", "hlp_unrolled_forward",
-           "hlp_unrolled_backward", "hlp_profile_iterations", "hlp_lp_destroy", "hlp_last_error")
+           "hlp_unrolled_backward", "hlp_profile_iterations", "hlp_solve_static", "hlp_lp_destroy",
+           "hlp_last_error")
 
 
 class HlpParams(C.Structure):
@@ -92,6 +93,8 @@ def lib():
         L.hlp_unrolled_forward.argtypes = [P, C.POINTER(HlpParams), I32, I32, I32, P, P, P, P, P, SZ]
         L.hlp_unrolled_backward.argtypes = [P, P, SZ] + [P] * 7
         L.hlp_profile_iterations.argtypes = [P, C.POINTER(HlpParams), I32, C.POINTER(C.c_double)]
+        L.hlp_solve_static.argtypes = [I32, I32, I64] + [P] * 8 + [C.POINTER(HlpParams), P, P, P, P,
+                                                                   C.POINTER(HlpInfo)]
         L.hlp_lp_destroy.argtypes = [P]
         L.hlp_lp_destroy.restype = None
         L.hlp_last_error.argtypes = []
@@ -206,6 +209,17 @@ def hlp_profile_iterations(lp, params, iters):
     out = (C.c_double * 4)()
     _check(lib().hlp_profile_iterations(lp, C.byref(params) if params is not None else None, iters, out))
     return dict(primal_ms=out[0], dual_ms=out[1], iter_ms=out[2], iters=int(out[3]))
+
+
+def hlp_solve_static(m, n, nnz, row_ptr, col_idx, val, c, lc, uc, lv, uv, params=None, stream=None,
+                     x=None, y=None, r=None) -> HlpInfo:
+    """Setup and solve in one call on the library's static device scratch
+    (no device allocation inside; see include/hlp.h)."""
+    info = HlpInfo()
+    _check(lib().hlp_solve_static(m, n, nnz, _ptr(row_ptr), _ptr(col_idx), _ptr(val), _ptr(c), _ptr(lc),
+                                  _ptr(uc), _ptr(lv), _ptr(uv), C.byref(params) if params is not None else None,
+                                  _stream(stream), _ptr(x), _ptr(y), _ptr(r), C.byref(info)))
+    return info
 
 
 def hlp_lp_destroy(lp):
