@@ -213,6 +213,7 @@ def measure_skewed(dev, lp, name, rate_iters, time_limit, profile_iters):
     setup = time.perf_counter() - t0
     _, _, eta, power_iters = p.scaling()
     out = {"workload": describe(name, lp), "setup_s": round(setup, 3), "power_iters": power_iters,
+           "workspace_gb": round(p.workspace.numel() / 1e9, 2),
            "column_panels": p.panels()[0], "long_rows": p.panels()[1], "narrow_panels": p.dense()[0],
            "dense_rows": p.dense()[1]}
     p.solve(max_iter=64, tol=1e-8, want_r=False)
@@ -492,8 +493,9 @@ def main():
     torch.cuda.synchronize()
     setup_wall = time.perf_counter() - t0
     _, _, eta, power_iters = prob.scaling()
+    workspace_gb = round(prob.workspace.numel() / 1e9, 2)
     log(f"# {HEADLINE}: setup {setup_wall:.2f} s (power iterations {power_iters}), panels {prob.panels()}, "
-        f"dense {prob.dense()}")
+        f"dense {prob.dense()}, workspace {workspace_gb} GB")
     for _ in range(args.warmup):
         prob.solve(tol=1e-8, max_iter=args.step_iters, want_r=False)
     torch.cuda.synchronize()
@@ -555,7 +557,7 @@ def main():
                    "step": f"one FP64 solve from the all-zero start, paper settings, tol 1e-8, capped at "
                            f"{args.step_iters} iterations (a check every 64)",
                    "seed": 1, "global_batch": 1, "parallelism": "single GPU"},
-        "setup_s": round(setup_wall, 3), "power_iters": power_iters, "eta": eta,
+        "setup_s": round(setup_wall, 3), "power_iters": power_iters, "eta": eta, "workspace_gb": workspace_gb,
         "time_to_tol_s": fp64_tl["time_to_tol_s"], "fp64_time_limited": fp64_tl, "mixed": mixed,
         "roofline": roofline, "cpu_baseline": cpu, **extra,
     }

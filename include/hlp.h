@@ -170,6 +170,19 @@ hlp_err hlp_params_default(hlp_params* p);
 hlp_err hlp_workspace_bytes(int32_t m, int32_t n, int64_t nnz, const hlp_params* p, size_t* bytes);
 
 /*
+ * Device workspace for this particular matrix: as hlp_workspace_bytes, but
+ * the column-panel layout is sized for the rows row_ptr describes (host
+ * int64[m+1], the CSR row pointers of the matrix that will be passed to
+ * hlp_lp_create) instead of for the worst rows (m, n, nnz) allow.  At most
+ * hlp_workspace_bytes.  hlp_lp_create accepts a workspace of this size for
+ * that matrix and parameters (it reads the row pointers back to lay it out).
+ * Errors: HLP_EINVAL for NULL pointers or row pointers that do not start at 0,
+ * end at nnz and never decrease; HLP_EUNSUPPORTED as hlp_workspace_bytes.
+ */
+hlp_err hlp_workspace_bytes_csr(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, const hlp_params* p,
+                                size_t* bytes);
+
+/*
  * Build a handle: validate, canonical CSR copy, explicit transpose, diagonal
  * rescaling (Ruiz then Pock-Chambolle; the paper's Sec. 4 notes that the
  * iteration runs on a preconditioned LP while termination is judged on the
@@ -182,13 +195,14 @@ hlp_err hlp_workspace_bytes(int32_t m, int32_t n, int64_t nnz, const hlp_params*
  *   lc, uc   device double[m]   row bounds, lc <= uc, lc != +inf, uc != -inf
  *   lv, uv   device double[n]   column bounds, same rules
  *   p        host               [setup] fields are used; NULL = defaults
- *   workspace, workspace_bytes  device buffer of at least hlp_workspace_bytes(),
- *                               256-byte aligned
+ *   workspace, workspace_bytes  device buffer of at least hlp_workspace_bytes() (or
+ *                               hlp_workspace_bytes_csr() of this matrix), 256-byte aligned
  *   hip_stream                  hipStream_t all work goes to (NULL = default stream)
  *   out      host               receives the handle
  *
  * The input arrays are copied (the caller may free or reuse them after the
- * call).  Errors: HLP_EINVAL for any violated rule above (NaN anywhere
+ * call).  workspace_bytes may be the hlp_workspace_bytes_csr size of this
+ * matrix.  Errors: HLP_EINVAL for any violated rule above (NaN anywhere
  * included) or a misaligned/small workspace (HLP_ENOMEM if small);
  * HLP_EHIP on a HIP failure.  On error *out is NULL.
  */

@@ -16,7 +16,7 @@ from .hlp import (FP64, MIXED, HLP_OK, ITER_LIMIT, NUMERICAL, OPTIMAL, STATUS_NA
                   HlpCheck, HlpError, HlpInfo, HlpParams, hlp_check_log, hlp_last_error, hlp_lp_create, hlp_lp_destroy,
                   hlp_lp_panels, hlp_lp_scaling, hlp_lp_transpose, hlp_lp_update_vectors, hlp_params_default,
                   hlp_profile_iterations, hlp_solve, hlp_tape_bytes, hlp_unrolled_backward,
-                  hlp_unrolled_forward, hlp_workspace_bytes, lib)
+                  hlp_unrolled_forward, hlp_workspace_bytes, hlp_workspace_bytes_csr, lib)
 
 __all__ = ["Problem", "solve", "HlpError", "FP64", "MIXED", "OPTIMAL", "ITER_LIMIT", "TIME_LIMIT",
            "NUMERICAL", "STATUS_NAMES", "hlp_params_default"]
@@ -67,7 +67,9 @@ class Problem:
         self.setup = dict(setup)
         self.params = hlp_params_default(**self.setup)
         self.precision = self.params.precision
-        nbytes = hlp_workspace_bytes(self.m, self.n, self.nnz, self.params)
+        # the workspace sized for this matrix's rows (at most the worst case for (m, n, nnz))
+        rp_host = rp.cpu().numpy() if hasattr(rp, "cpu") else np.asarray(rp)
+        nbytes = hlp_workspace_bytes_csr(self.m, self.n, self.nnz, rp_host, self.params)
         self._ws_base, self.workspace = _aligned_bytes(nbytes, self.device)
         self.handle = hlp_lp_create(self.m, self.n, self.nnz, self.row_ptr, self.col_idx, self.val,
                                     *self.vectors, self.params, self.workspace, stream)

@@ -71,14 +71,12 @@ int32_t panel_count(int32_t n, const hlp_params* p) {
   return (int32_t)std::min<int64_t>(P, 1024);
 }
 
-size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t precision, int32_t panels,
-             int32_t panel_row_min, int32_t dense_row_min) {
-  Carver c{static_cast<char*>(base)};
-  const bool mixed = precision == HLP_MIXED;
-  const int64_t N = std::max<int64_t>(m, n);
-  hlp_lp tmp;
-  hlp_lp* L = lp ? lp : &tmp;
-  // panel layout capacity: at most nnz / (T + 1) rows are longer than T
+// Capacities of the panel layout for the worst row-length pattern that
+// (m, n, nnz) allow: at most nnz / (T + 1) rows longer than T, at most
+// min(m, nnz / Ld, kMaxDense) dense rows, every part of the matrix as large
+// as the whole.
+Caps worst_caps(int32_t m, int32_t n, int64_t nnz, int32_t panels, int32_t panel_row_min, int32_t dense_row_min) {
+  Caps k;
   int64_t nLmax = 0, R = 0;
   if (panels > 0 && panel_row_min >= 1) {
     nLmax = std::min<int64_t>(m, nnz / ((int64_t)panel_row_min + 1));
@@ -86,21 +84,90 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
     if (R + 2 >= (int64_t(1) << 30)) nLmax = R = 0;  // int32 device indexing of the panel rows
   }
   if (nLmax == 0) panels = 0;
+  k.panels = panels;
+  k.rows = nLmax;
+  k.long_rows = nLmax;
+  int64_t nDmax = 0, PT = 0;
+  if (panels > 0 && dense_row_min > panel_row_min) {
+    const int64_t PD = ((int64_t)n + kDenseW - 1) / kDenseW;
+    nDmax = std::min<int64_t>(std::min<int64_t>(m, nnz / dense_row_min), kMaxDense);
+    PT = (nDmax + kDenseWT - 1) / kDenseWT;
+    if (nDmax == 0 || PD * nDmax + PD + 2 >= (int64_t(1) << 30) || PT * n + PT + 2 >= (int64_t(1) << 30))
+      nDmax = PT = 0;
+  }
+  k.dense_rows = nDmax;
+  k.dense_limit = nDmax;
+  k.slices = PT;
+  k.nnz_short = k.nnz_long = k.nnz_dense = k.nnz_rest = nnz;
+  return k;
+}
+
+Caps exact_caps(int32_t m, int32_t n, int64_t nnz, const int64_t* rp, int32_t panels, int32_t panel_row_min,
+                int32_t dense_row_min, bool automatic) {
+  const Caps w = worst_caps(m, n, nnz, panels, panel_row_min, dense_row_min);
+  Caps k;
+  if (w.panels <= 0 || m == 0 || n == 0 || nnz == 0) return k;
+  const int64_t T = panel_row_min;
+  int64_t Ld = w.dense_rows == 0 ? 0 : dense_row_min;
+  int64_t nL = 0, nD = 0, nnzS = 0, nnzL = 0, nnzD = 0;
+  auto count = [&]() {
+    nL = nD = nnzS = nnzL = nnzD = 0;
+    for (int32_t i = 0; i < m; ++i) {
+      const int64_t len = rp[i + 1] - rp[i];
+      if (Ld > 0 && len >= Ld) {
+        ++nD;
+        nnzD += len;
+      } else if (len > T) {
+        ++nL;
+        nnzL += len;
+      } else {
+        nnzS += len;
+      }
+    }
+  };
+  // the same threshold doubling as hlp_lp_create (build_panels)
+  for (;;) {
+    count();
+    if (nD <= w.dense_limit || Ld == 0) break;
+    Ld = Ld > n / 2 ? 0 : 2 * Ld;
+  }
+  if (nL + nD < 1 || nL + nD > w.rows || nD > w.dense_rows) return k;
+  if (automatic && 2 * (nnz - nnzS) < nnz) return k;
+  k.panels = w.panels;
+  k.rows = nL + nD;
+  k.long_rows = nL;
+  k.dense_rows = nD;
+  k.dense_limit = w.dense_limit;
+  k.nnz_short = nnzS;
+  k.nnz_long = nnzL;
+  k.nnz_dense = nnzD;
+  if (nD > 0 && 2 * nnzD >= nnz) {
+    k.slices = (nD + kDenseWT - 1) / kDenseWT;
+    k.nnz_rest = nnz - nnzD;
+  }
+  return k;
+}
+
+size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t precision, const Caps& k) {
+  Carver c{static_cast<char*>(base)};
+  const bool mixed = precision == HLP_MIXED;
+  const int64_t N = std::max<int64_t>(m, n);
+  hlp_lp tmp;
+  hlp_lp* L = lp ? lp : &tmp;
+  const int32_t panels = k.rows > 0 ? k.panels : 0;
+  const int64_t nLmax = panels > 0 ? k.rows : 0;     // long and dense rows
+  const int64_t R = (int64_t)panels * (panels > 0 ? k.long_rows : 0);
   L->panels = panels;  // reserved count; hlp_lp_create may switch the layout off
   L->nL_cap = (int32_t)nLmax;
   // dense rows (at least dense_row_min nonzeros): narrow panels of kDenseW columns
-  int64_t nDmax = 0, RD = 0, PD = 0, GD = 0;
-  int64_t PT = 0, RT = 0;
-  if (panels > 0 && dense_row_min > panel_row_min) {
-    PD = ((int64_t)n + kDenseW - 1) / kDenseW;
-    GD = (PD + kDenseGroup - 1) / kDenseGroup;
-    nDmax = std::min<int64_t>(std::min<int64_t>(m, nnz / dense_row_min), kMaxDense);
-    RD = PD * nDmax;
-    PT = (nDmax + kDenseWT - 1) / kDenseWT;
-    RT = PT * n;
-    if (nDmax == 0 || RD + PD + 2 >= (int64_t(1) << 30) || RT + PT + 2 >= (int64_t(1) << 30)) nDmax = RD = PT = RT = 0;
-  }
+  const int64_t nDmax = panels > 0 ? k.dense_rows : 0;
+  const int64_t PD = nDmax > 0 ? ((int64_t)n + kDenseW - 1) / kDenseW : 0;
+  const int64_t GD = (PD + kDenseGroup - 1) / kDenseGroup;
+  const int64_t RD = PD * nDmax;
+  const int64_t PT = nDmax > 0 ? k.slices : 0;
+  const int64_t RT = PT * n;
   L->nD_cap = (int32_t)nDmax;
+  L->nD_limit = (int32_t)(panels > 0 ? k.dense_limit : 0);
   L->dense_P = (int32_t)PD;
   L->dense_PT_cap = (int32_t)PT;
   const int64_t RB = std::max<int64_t>(std::max<int64_t>(N, R), std::max(RD, RT));
@@ -187,13 +254,13 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
     L->plid = c.take<int32_t>((int64_t)m + 1);
     L->lbits = c.take<uint32_t>(((int64_t)m + 31) / 32);
     L->sp = c.take<int32_t>((int64_t)m + 1);
-    L->scol = c.take<int32_t>(nnz);
-    L->sval = c.take<double>(nnz);
-    L->sval32 = mixed ? c.take<float>(nnz) : nullptr;
+    L->scol = c.take<int32_t>(k.nnz_short);
+    L->sval = c.take<double>(k.nnz_short);
+    L->sval32 = mixed ? c.take<float>(k.nnz_short) : nullptr;
     L->pp = c.take<int32_t>(R + 1);
-    L->pcol = c.take<int32_t>(nnz);
-    L->pval = c.take<double>(nnz);
-    L->pval32 = mixed ? c.take<float>(nnz) : nullptr;
+    L->pcol = c.take<int32_t>(k.nnz_long);
+    L->pval = c.take<double>(k.nnz_long);
+    L->pval32 = mixed ? c.take<float>(k.nnz_long) : nullptr;
     L->ppart = c.take<double>(R);
     L->rbS = c.take<int32_t>((int64_t)m + 2);
     L->rbxS = c.take<int32_t>(4 * ((int64_t)m + 1));
@@ -208,26 +275,28 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
   }
   if (nDmax > 0) {
     L->ppD = c.take<int32_t>(RD + 1);
-    L->pcolD = c.take<uint16_t>(nnz);
-    L->pvalD = c.take<double>(nnz);
-    L->pval32D = mixed ? c.take<float>(nnz) : nullptr;
+    L->pcolD = c.take<uint16_t>(k.nnz_dense);
+    L->pvalD = c.take<double>(k.nnz_dense);
+    L->pval32D = mixed ? c.take<float>(k.nnz_dense) : nullptr;
     L->partD = c.take<double>(RD);
     L->part2D = c.take<double>(GD * nDmax);
-    const int64_t bD = std::min<int64_t>(RD, row_block_bound(RD, nnz, PD));
+    const int64_t bD = std::min<int64_t>(RD, row_block_bound(RD, k.nnz_dense, PD));
     L->rbD = c.take<int32_t>(RD + 2);
     L->capD_blocks = bD + 1;
     L->rbxD = c.take<int32_t>(4 * (bD + 1));
     L->tilesD = c.take<int32_t>(4 * (bD + 1));
+  }
+  if (PT > 0) {
     L->cpR = c.take<int32_t>((int64_t)n + 1);
-    L->rowR = c.take<int32_t>(nnz);
-    L->tvalR = c.take<double>(nnz);
-    L->tval32R = mixed ? c.take<float>(nnz) : nullptr;
+    L->rowR = c.take<int32_t>(k.nnz_rest);
+    L->tvalR = c.take<double>(k.nnz_rest);
+    L->tval32R = mixed ? c.take<float>(k.nnz_rest) : nullptr;
     L->ppT = c.take<int32_t>(RT + 1);
-    L->rowT = c.take<uint16_t>(nnz);
-    L->tvalT = c.take<double>(nnz);
-    L->tval32T = mixed ? c.take<float>(nnz) : nullptr;
+    L->rowT = c.take<uint16_t>(k.nnz_dense);
+    L->tvalT = c.take<double>(k.nnz_dense);
+    L->tval32T = mixed ? c.take<float>(k.nnz_dense) : nullptr;
     L->partT = c.take<double>(RT);
-    const int64_t bT = std::min<int64_t>(RT, row_block_bound(RT, nnz, PT));
+    const int64_t bT = std::min<int64_t>(RT, row_block_bound(RT, k.nnz_dense, PT));
     L->rbR = c.take<int32_t>((int64_t)n + 2);
     L->rbxR = c.take<int32_t>(4 * ((int64_t)n + 1));
     L->rbT2 = c.take<int32_t>(RT + 2);
@@ -307,8 +376,38 @@ hlp_err hlp_workspace_bytes(int32_t m, int32_t n, int64_t nnz, const hlp_params*
   hlp_params d;
   hlp_params_default(&d);
   if (!p) p = &d;
-  *bytes = carve(nullptr, nullptr, m, n, nnz, p->precision, panel_count(n, p), p->panel_row_min,
-                 p->dense_row_min);
+  *bytes = carve(nullptr, nullptr, m, n, nnz, p->precision,
+                 worst_caps(m, n, nnz, panel_count(n, p), p->panel_row_min, p->dense_row_min));
+  return HLP_OK;
+}
+
+static hlp_err check_row_ptr_host(int32_t m, int64_t nnz, const int64_t* rp) {
+  if (rp[0] != 0 || rp[m] != nnz) {
+    set_error("row_ptr must start at 0 and end at nnz");
+    return HLP_EINVAL;
+  }
+  for (int32_t i = 0; i < m; ++i)
+    if (rp[i] > rp[i + 1]) {
+      set_error("row_ptr must be nondecreasing");
+      return HLP_EINVAL;
+    }
+  return HLP_OK;
+}
+
+hlp_err hlp_workspace_bytes_csr(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, const hlp_params* p,
+                                size_t* bytes) {
+  if (!bytes || !row_ptr) {
+    set_error("hlp_workspace_bytes_csr: NULL row_ptr or output");
+    return HLP_EINVAL;
+  }
+  HLP_TRY(check_sizes(m, n, nnz));
+  hlp_params d;
+  hlp_params_default(&d);
+  if (!p) p = &d;
+  HLP_TRY(check_row_ptr_host(m, nnz, row_ptr));
+  *bytes = carve(nullptr, nullptr, m, n, nnz, p->precision,
+                 exact_caps(m, n, nnz, row_ptr, panel_count(n, p), p->panel_row_min, p->dense_row_min,
+                            p->column_panels == -1));
   return HLP_OK;
 }
 
@@ -349,7 +448,7 @@ static hlp_err build_panels(hlp_lp* lp, int32_t P, int32_t T, int32_t Ld, bool a
     HLP_HIP(launch_panel_split(lp, T, Ld, lp->flags));
     HLP_HIP(hipMemcpyAsync(cnt, lp->flags, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, lp->stream));
     HLP_HIP(hipStreamSynchronize(lp->stream));
-    if (cnt[2] <= lp->nD_cap || Ld == 0) break;
+    if (cnt[2] <= lp->nD_limit || Ld == 0) break;
     Ld = Ld > lp->n / 2 ? 0 : 2 * Ld;
   }
   lp->dense_min = Ld;
@@ -357,6 +456,12 @@ static hlp_err build_panels(hlp_lp* lp, int32_t P, int32_t T, int32_t Ld, bool a
   const int64_t nnz_split = lp->nnz - cnt[1];
   if (nL + nD < 1 || nL + nD > lp->nL_cap || nD > lp->nD_cap) return HLP_OK;
   if (automatic && 2 * nnz_split < lp->nnz) return HLP_OK;
+  // a layout sized for this matrix's rows (hlp_workspace_bytes_csr) must see
+  // the rows it was sized for
+  if (lp->exact_layout && (nL + nD != lp->nL_cap || nD != lp->nD_cap || cnt[1] != lp->cap_nnz_short)) {
+    set_error("column panels: the rows differ from those the workspace layout was sized for");
+    return HLP_EUNSUPPORTED;
+  }
   lp->panels = P;
   lp->nL = nL;
   lp->nD = nD;
@@ -431,6 +536,10 @@ static hlp_err build_panels(hlp_lp* lp, int32_t P, int32_t T, int32_t Ld, bool a
       HLP_HIP(hipStreamSynchronize(lp->stream));
       return HLP_OK;
     }
+    if (lp->dense_PT_cap == 0 || (lp->exact_layout && nnzD != lp->cap_nnz_dense)) {
+      set_error("dense rows: the primal split was not reserved for these rows");
+      return HLP_EUNSUPPORTED;
+    }
     lp->dense_PT = (nD + lp->dense_wT - 1) / lp->dense_wT;
     HLP_HIP(launch_dense_transpose(lp, lp->flags));
     HLP_HIP(hipMemcpyAsync(cnt, lp->flags, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, lp->stream));
@@ -493,10 +602,12 @@ namespace hlp {
 // hlp_lp): argument checks, workspace layout, validation, copy, transpose,
 // rescaling, panel layout, scaled vectors and the stepsize.  On error the
 // object may hold pointers into the workspace and must be discarded.
+// size_to_rows: a workspace below hlp_workspace_bytes may still hold a panel
+// layout sized for the matrix's rows (read back from row_ptr on the host).
 hlp_err setup_into(hlp_lp* lp, int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
                    const double* val, const double* c, const double* lc, const double* uc, const double* lv,
                    const double* uv, const hlp_params* p, void* workspace, size_t workspace_bytes,
-                   void* hip_stream) {
+                   void* hip_stream, bool size_to_rows) {
   HLP_TRY(check_sizes(m, n, nnz));
   if (!row_ptr || (nnz > 0 && (!col_idx || !val)) || !workspace) {
     set_error("hlp_lp_create: NULL input pointer");
@@ -524,7 +635,21 @@ hlp_err setup_into(hlp_lp* lp, int32_t m, int32_t n, int64_t nnz, const int64_t*
     return HLP_EINVAL;
   }
   const int32_t P = panel_count(n, p);
-  size_t need = carve(nullptr, nullptr, m, n, nnz, p->precision, P, p->panel_row_min, p->dense_row_min);
+  Caps caps = worst_caps(m, n, nnz, P, p->panel_row_min, p->dense_row_min);
+  size_t need = carve(nullptr, nullptr, m, n, nnz, p->precision, caps);
+  bool exact = false;
+  if (workspace_bytes < need && size_to_rows && caps.panels > 0) {
+    // smaller than the worst case: size the panel layout for this matrix's
+    // rows (what hlp_workspace_bytes_csr reports)
+    std::vector<int64_t> rp((size_t)m + 1);
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    HLP_HIP(hipMemcpyAsync(rp.data(), row_ptr, sizeof(int64_t) * ((size_t)m + 1), hipMemcpyDeviceToHost, st));
+    HLP_HIP(hipStreamSynchronize(st));
+    HLP_TRY(check_row_ptr_host(m, nnz, rp.data()));
+    caps = exact_caps(m, n, nnz, rp.data(), P, p->panel_row_min, p->dense_row_min, p->column_panels == -1);
+    need = carve(nullptr, nullptr, m, n, nnz, p->precision, caps);
+    exact = true;
+  }
   if (workspace_bytes < need) {
     set_error("workspace too small: need " + std::to_string(need) + " bytes");
     return HLP_ENOMEM;
@@ -535,7 +660,10 @@ hlp_err setup_into(hlp_lp* lp, int32_t m, int32_t n, int64_t nnz, const int64_t*
   lp->nnz = nnz;
   lp->stream = reinterpret_cast<hipStream_t>(hip_stream);
   lp->precision = p->precision;
-  carve(lp, workspace, m, n, nnz, p->precision, P, p->panel_row_min, p->dense_row_min);
+  carve(lp, workspace, m, n, nnz, p->precision, caps);
+  lp->exact_layout = exact;
+  lp->cap_nnz_short = caps.nnz_short;
+  lp->cap_nnz_dense = caps.nnz_dense;
   auto fail = [](hlp_err e) { return e; };
   // 1. row pointers, then the rows themselves
   if (hipError_t e = launch_fill(reinterpret_cast<double*>(lp->flags), 0.0, 1, lp->stream); e != hipSuccess)
@@ -579,7 +707,8 @@ hlp_err setup_into(hlp_lp* lp, int32_t m, int32_t n, int64_t nnz, const int64_t*
   // 3. rescaling of A, then the vectors
   if (hipError_t e = launch_rescale(lp, p->ruiz_iters, p->pock_chambolle); e != hipSuccess)
     return fail(hip_fail(e, "rescale"));
-  if (hlp_err e = build_panels(lp, P, p->panel_row_min, p->dense_row_min, p->column_panels == -1); e != HLP_OK)
+  if (hlp_err e = build_panels(lp, lp->panels, p->panel_row_min, p->dense_row_min, p->column_panels == -1);
+      e != HLP_OK)
     return fail(e);
   if (hlp_err e = validate_and_scale_vectors(lp, c, lc, uc, lv, uv); e != HLP_OK) return fail(e);
   // 4. stepsize
@@ -629,7 +758,7 @@ hlp_err hlp_lp_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr,
     return HLP_ENOMEM;
   }
   const hlp_err e = setup_into(lp, m, n, nnz, row_ptr, col_idx, val, c, lc, uc, lv, uv, p, workspace,
-                               workspace_bytes, hip_stream);
+                               workspace_bytes, hip_stream, true);
   if (e != HLP_OK) {
     delete lp;
     return e;

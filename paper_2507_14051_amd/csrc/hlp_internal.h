@@ -107,6 +107,11 @@ struct hlp_lp {
   // lrow[nL + d] in narrow panel q.  A tile = consecutive row blocks of one
   // narrow panel, reduced by one block with the panel's slice of xbar in LDS.
   int32_t dense_min = 0, dense_P = 0, dense_w = 0, nD = 0, nD_cap = 0;
+  int32_t nD_limit = 0;  // more dense rows than this: the threshold is doubled
+  // the layout was sized for this matrix's rows (long + dense, dense, short
+  // nonzeros and dense nonzeros exactly what build_panels must find)
+  bool exact_layout = false;
+  int64_t cap_nnz_short = 0, cap_nnz_dense = 0;
   int32_t *dlid = nullptr, *ppD = nullptr;
   uint16_t* pcolD = nullptr;  // column offset in the narrow panel
   double* pvalD = nullptr;
@@ -197,12 +202,29 @@ hlp_err hip_fail(hipError_t e, const char* what);
 hlp_err setup_into(hlp_lp* lp, int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
                    const double* val, const double* c, const double* lc, const double* uc, const double* lv,
                    const double* uv, const hlp_params* p, void* workspace, size_t workspace_bytes,
-                   void* hip_stream);
+                   void* hip_stream, bool size_to_rows);
 
 // ---------------------------------------------------------------- layout
+// Capacities of the column-panel layout that the workspace reserves.
+struct Caps {
+  int32_t panels = 0;        // wide panels reserved (0: no panel layout)
+  int64_t rows = 0;          // long and dense rows together
+  int64_t long_rows = 0;     // long rows (wide panels)
+  int64_t dense_rows = 0;    // dense rows (narrow panels); 0: none
+  int64_t dense_limit = 0;   // more dense rows than this double the threshold
+  int64_t slices = 0;        // slices of the primal split (0: not reserved)
+  int64_t nnz_short = 0, nnz_long = 0, nnz_dense = 0;  // nonzeros of AS, AP, AD (and ATD)
+  int64_t nnz_rest = 0;      // nonzeros of ATR
+};
+// For any rows an (m, n, nnz) matrix can have.
+Caps worst_caps(int32_t m, int32_t n, int64_t nnz, int32_t panels, int32_t panel_row_min, int32_t dense_row_min);
+// For the rows of this matrix (host row pointers, already validated): what
+// hlp_lp_create's layout rules (thresholds, the automatic rule, the primal
+// split) will build from them.
+Caps exact_caps(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, int32_t panels, int32_t panel_row_min,
+                int32_t dense_row_min, bool automatic);
 // Carve the workspace.  With lp->... == nullptr base, only computes the size.
-size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t precision, int32_t panels,
-             int32_t panel_row_min, int32_t dense_row_min);
+size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t precision, const Caps& caps);
 constexpr int32_t kDenseW = 2048;     // columns per narrow panel (its FP64 slice: 16 KB of LDS; < 65536)
 // Compact dense indices per slice of the primal split (< 65536).  4096 halves
 // the slice partials but its 32 KB slice leaves three blocks per CU, and the

@@ -72,7 +72,7 @@ hlp_err hlp_solve_static(int32_t m, int32_t n, int64_t nnz, const int64_t* row_p
   hlp_lp lp;
   lp.keep_log = false;
   HLP_TRY(hlp::setup_into(&lp, m, n, nnz, row_ptr, col_idx, val, c, lc, uc, lv, uv, &q, ws, kStaticBytes,
-                          hip_stream));
+                          hip_stream, false));
   return hlp_solve(&lp, &q, nullptr, nullptr, x, y, r, info, nullptr);
 }
 

@@ -18,10 +18,10 @@ FP64, MIXED = 0, 1
 STATUS_NAMES = {OPTIMAL: "OPTIMAL", ITER_LIMIT: "ITER_LIMIT", TIME_LIMIT: "TIME_LIMIT", NUMERICAL: "NUMERICAL"}
 
 # The exported symbols, in the order of include/hlp.h.
-SYMBOLS = ("hlp_params_default", "hlp_workspace_bytes", "hlp_lp_create", "hlp_lp_update_vectors",
-           "hlp_solve", "hlp_check_log", "hlp_lp_scaling", "hlp_lp_transpose", "hlp_lp_panels", "hlp_tape_bytes", "hlp_unrolled_forward",
-           "hlp_unrolled_backward", "hlp_profile_iterations", "hlp_solve_static", "hlp_lp_destroy",
-           "hlp_last_error")
+SYMBOLS = ("hlp_params_default", "hlp_workspace_bytes", "hlp_workspace_bytes_csr", "hlp_lp_create",
+           "hlp_lp_update_vectors", "hlp_solve", "hlp_check_log", "hlp_lp_scaling", "hlp_lp_transpose",
+           "hlp_lp_panels", "hlp_tape_bytes", "hlp_unrolled_forward", "hlp_unrolled_backward",
+           "hlp_profile_iterations", "hlp_solve_static", "hlp_lp_destroy", "hlp_last_error")
 
 
 class HlpParams(C.Structure):
@@ -82,6 +82,7 @@ def lib():
         P, I64, I32, SZ = C.c_void_p, C.c_int64, C.c_int32, C.c_size_t
         L.hlp_params_default.argtypes = [C.POINTER(HlpParams)]
         L.hlp_workspace_bytes.argtypes = [I32, I32, I64, C.POINTER(HlpParams), C.POINTER(SZ)]
+        L.hlp_workspace_bytes_csr.argtypes = [I32, I32, I64, P, C.POINTER(HlpParams), C.POINTER(SZ)]
         L.hlp_lp_create.argtypes = [I32, I32, I64] + [P] * 8 + [C.POINTER(HlpParams), P, SZ, P, C.POINTER(P)]
         L.hlp_lp_update_vectors.argtypes = [P] * 6
         L.hlp_solve.argtypes = [P, C.POINTER(HlpParams), P, P, P, P, P, C.POINTER(HlpInfo), P]
@@ -138,6 +139,18 @@ def hlp_params_default(**overrides) -> HlpParams:
 def hlp_workspace_bytes(m, n, nnz, params=None) -> int:
     out = C.c_size_t(0)
     _check(lib().hlp_workspace_bytes(m, n, nnz, C.byref(params) if params is not None else None, C.byref(out)))
+    return out.value
+
+
+def hlp_workspace_bytes_csr(m, n, nnz, row_ptr, params=None) -> int:
+    """Workspace for this matrix (row_ptr: host int64 array of m + 1 row pointers)."""
+    import numpy as np
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    if rp.size != m + 1:
+        raise ValueError("row_ptr must hold m + 1 entries")
+    out = C.c_size_t(0)
+    _check(lib().hlp_workspace_bytes_csr(m, n, nnz, rp.ctypes.data_as(C.c_void_p),
+                                         C.byref(params) if params is not None else None, C.byref(out)))
     return out.value
 
 

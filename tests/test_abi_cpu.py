@@ -118,3 +118,27 @@ def test_panel_parameters_and_workspace():
                              C.c_size_t(1 << 30), None, C.byref(out))
         assert rc == -1, bad
         assert b"panel" in L.hlp_last_error()
+
+
+def test_workspace_sized_for_the_rows():
+    """hlp_workspace_bytes_csr sizes the column-panel layout for the matrix's
+    own rows: never above the worst case for (m, n, nnz), equal to it when no
+    panel layout is used, well below it for skewed rows; bad row pointers are
+    rejected."""
+    import lpgen
+    from paper_2507_14051_amd import HlpError, hlp_params_default, hlp_workspace_bytes, hlp_workspace_bytes_csr
+    lp = lpgen.config("c1", seed=1)
+    p = hlp_params_default()
+    assert hlp_workspace_bytes_csr(lp.m, lp.n, lp.nnz, lp.A.indptr, p) == hlp_workspace_bytes(lp.m, lp.n, lp.nnz, p)
+    sk = lpgen.gen(3000, 20000, zipf_alpha=1.3, cap=9000, eq_frac=0.3, free_frac=0.2, values="normal", seed=7)
+    for kw in (dict(column_panels=16, panel_row_min=8, dense_row_min=512), dict(column_panels=16, panel_row_min=8),
+               dict(column_panels=8, panel_row_min=8, dense_row_min=0), dict(column_panels=8, precision=1)):
+        q = hlp_params_default(**kw)
+        w = hlp_workspace_bytes(sk.m, sk.n, sk.nnz, q)
+        e = hlp_workspace_bytes_csr(sk.m, sk.n, sk.nnz, sk.A.indptr, q)
+        assert e < w, kw
+    bad = sk.A.indptr.copy()
+    bad[5], bad[6] = bad[6], bad[5]
+    with pytest.raises(HlpError) as err:
+        hlp_workspace_bytes_csr(sk.m, sk.n, sk.nnz, bad, p)
+    assert err.value.code == -1

@@ -342,3 +342,34 @@ def test_streamed_matrix_loads_change_nothing(layout, precision):
     if precision == 0:
         ref = oracle.solve(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, Params(tol=0.0, max_iter=200, eta_override=eta))
         assert rel(outs[1]["x"], ref.x) <= TOL and rel(outs[1]["y"], ref.y) <= TOL
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_workspace_sized_for_the_rows_gives_the_same_bits(precision):
+    """A handle laid out in the workspace sized for the matrix's rows
+    (hlp_workspace_bytes_csr, what Problem allocates) and one laid out for the
+    worst rows (hlp_workspace_bytes) build the same panel layout and give the
+    same bits; the row-sized workspace is the smaller one."""
+    import torch
+    from paper_2507_14051_amd import hlp
+    lp = lpgen.gen(3000, 20000, zipf_alpha=1.3, cap=9000, eq_frac=0.3, free_frac=0.2, values="normal", seed=7)
+    announce(f"row-sized vs worst-case workspace precision={precision}")
+    kw = dict(column_panels=16, panel_row_min=8, dense_row_min=512, precision=precision)
+    a = problem(lp, **kw)
+    assert a.panels()[0] == 16 and a.dense()[1] > 0
+    oa = np_out(a.solve(tol=0.0, max_iter=300))
+    params = a.params_for()
+    worst = hlp.hlp_workspace_bytes(lp.m, lp.n, lp.nnz, params)
+    assert a.workspace.numel() < worst
+    base = torch.empty(worst + 256, dtype=torch.uint8, device="cuda:0")
+    off = (-base.data_ptr()) % 256
+    ws = base[off:off + worst]
+    h = hlp.hlp_lp_create(lp.m, lp.n, lp.nnz, a.row_ptr, a.col_idx, a.val, *a.vectors, params, ws)
+    assert hlp.hlp_lp_panels(h) == (*a.panels(), *a.dense())
+    f64 = dict(dtype=torch.float64, device="cuda:0")
+    x, y = torch.empty(lp.n, **f64), torch.empty(lp.m, **f64)
+    info = hlp.hlp_solve(h, hlp.hlp_params_default(**{**kw, "tol": 0.0, "max_iter": 300}), None, None, x, y)
+    hlp.hlp_lp_destroy(h)
+    a.close()
+    assert np.array_equal(oa["x"], x.cpu().numpy()) and np.array_equal(oa["y"], y.cpu().numpy())
+    assert info.iters == oa["info"]["iters"] == 300
