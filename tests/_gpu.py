@@ -26,12 +26,12 @@ def oracle_eta(lp, ruiz_iters=10, pock_chambolle=1):
     return cached[key]
 
 
-def problem(lp, eta=None, **setup):
+def problem(lp, eta=None, layout="auto", **setup):
     """The GPU handle for lp; eta (if given) replaces the GPU's power iteration."""
     from paper_2507_14051_amd import Problem
     if eta is not None:
         setup["eta_override"] = eta
-    return Problem(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, device="cuda:0", **setup)
+    return Problem(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, device="cuda:0", layout=layout, **setup)
 
 
 def np_out(out):

@@ -347,7 +347,7 @@ def test_streamed_matrix_loads_change_nothing(layout, precision):
 @pytest.mark.parametrize("precision", [0, 1])
 def test_workspace_sized_for_the_rows_gives_the_same_bits(precision):
     """A handle laid out in the workspace sized for the matrix's rows
-    (hlp_workspace_bytes_csr, what Problem allocates) and one laid out for the
+    (hlp_workspace_bytes_csr, Problem's layout="rows") and one laid out for the
     worst rows (hlp_workspace_bytes) build the same panel layout and give the
     same bits; the row-sized workspace is the smaller one."""
     import torch
@@ -355,7 +355,7 @@ def test_workspace_sized_for_the_rows_gives_the_same_bits(precision):
     lp = lpgen.gen(3000, 20000, zipf_alpha=1.3, cap=9000, eq_frac=0.3, free_frac=0.2, values="normal", seed=7)
     announce(f"row-sized vs worst-case workspace precision={precision}")
     kw = dict(column_panels=16, panel_row_min=8, dense_row_min=512, precision=precision)
-    a = problem(lp, **kw)
+    a = problem(lp, layout="rows", **kw)
     assert a.panels()[0] == 16 and a.dense()[1] > 0
     oa = np_out(a.solve(tol=0.0, max_iter=300))
     params = a.params_for()
