@@ -290,7 +290,7 @@ def measure_c2(dev, steps, profile_iters):
     return out
 
 
-def cpu_baseline(lp, name, rows_div=32, iters=64):
+def cpu_baseline(lp, name, rows_div=32, iters=32):
     """The FP64 CPU oracle as it stands on a bounded sample of the headline LP:
     the LP restricted to its first m/rows_div rows (rows are drawn
     independently, so the sample keeps the row-length law; all columns and
