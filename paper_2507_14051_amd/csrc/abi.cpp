@@ -199,7 +199,7 @@ size_t carve(hlp_lp* lp, void* base, int32_t m, int32_t n, int64_t nnz, int32_t 
   const int64_t ycopy = panels > 0 ? nLmax : 0;
   L->y = c.take<double>(m + ycopy);
   L->ya = c.take<double>(m);
-  L->yh = c.take<double>(m);
+  L->yh = c.take<double>(m + ycopy);  // with the same compact copy (column-side KKT over the split transpose)
   if (mixed) {
     L->x32 = c.take<float>(n);
     L->xa32 = c.take<float>(n);

@@ -137,6 +137,7 @@ struct hlp_lp {
   int64_t nb_dual_region = 0;   // blocks of the last check dual launch (its partials region)
   int64_t nb_primal_region = 0; // blocks of the last check primal launch (its partials region)
   int64_t nb_rows_region = 0;   // blocks of the last KKT-rows launch (its partials region)
+  int64_t nb_kkt_region = 0;    // blocks of the last KKT-columns launch (its partials region)
   int32_t nbS = 0, nbP = 0, nbPgrid = 0, nbC = 0;
   int32_t poff[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // blocks of XCD x: tabP[poff[x] .. poff[x+1])
   int64_t rbtmp_rows = 0;             // capacity of the row-block scratch (rows)

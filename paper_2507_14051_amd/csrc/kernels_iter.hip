@@ -717,6 +717,8 @@ struct KktColArgs {
   const int32_t* rb; const int32_t* cp; const int32_t* row; const double* tval;
   const double* yh; const double* xh; const double* ct; const double* lv; const double* uv;
   const double* dc; double* r_out; double* aty_out; double* partials;
+  const double* partT;  // if PT > 0: the dense rows' part of A~^T yhat, PT slice sums per column
+  int32_t PT, n;
 };
 
 template <bool MIXED>
@@ -730,7 +732,8 @@ __global__ __launch_bounds__(kBlock) void k_kkt_cols(KktColArgs p) {
     a0 = p.cp[j];
     a1 = p.cp[j + 1];
   }
-  const double acc = rb_dot<double>(p.row, p.tval, p.yh, p.cp[s], p.cp[e], a0, a1, own, e - s, lds);
+  double acc = rb_dot<double>(p.row, p.tval, p.yh, p.cp[s], p.cp[e], a0, a1, own, e - s, lds);
+  if (p.PT > 0 && own) acc += slice_sum(p.partT, p.PT, p.n, j);
   double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (own) {
     const double g = p.ct[j] - acc;
@@ -1287,9 +1290,29 @@ hipError_t launch_dual(hlp_lp* lp, const StepArgs& s) {
 hipError_t launch_kkt_cols(hlp_lp* lp, double* r_out) {
   if (lp->nbT == 0) return hipSuccess;
   KktColArgs a{lp->rbT, lp->cp, lp->row, lp->tval, lp->yh, lp->xh, lp->ct, lp->lvt, lp->uvt, lp->dc, r_out,
-               lp->atyc, region(lp, R_KKT)};
-  if (lp->precision == HLP_MIXED) hipLaunchKernelGGL(k_kkt_cols<true>, dim3(lp->nbT), dim3(kBlock), 0, lp->stream, a);
-  else hipLaunchKernelGGL(k_kkt_cols<false>, dim3(lp->nbT), dim3(kBlock), 0, lp->stream, a);
+               lp->atyc, region(lp, R_KKT), nullptr, 0, lp->n};
+  int32_t nb = lp->nbT;
+  if (lp->panels && lp->ntilesT > 0) {
+    // as the primal half-step: the dense rows' entries of A~^T yhat by the
+    // tiles of ATD (slices of yhat's compact copy in LDS), then ATR adds them
+    hipError_t e = refresh_long_y(lp, lp->yh);
+    if (e != hipSuccess) return e;
+    DenseDotArgs<double> da{reinterpret_cast<const int4*>(lp->tilesT), reinterpret_cast<const int4*>(lp->rbxT2),
+                            lp->ppT, lp->rowT, lp->tvalT, lp->yh + lp->m + lp->nL, lp->partT, lp->nD};
+    hipLaunchKernelGGL((k_dense_dot<double, false, kDenseWT>), dim3(lp->ntilesT), dim3(kBlock), 0, lp->stream, da);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    a.rb = lp->rbR;
+    a.cp = lp->cpR;
+    a.row = lp->rowR;
+    a.tval = lp->tvalR;
+    a.partT = lp->partT;
+    a.PT = lp->dense_PT;
+    nb = lp->nbR;
+  }
+  lp->nb_kkt_region = nb;
+  if (nb == 0) return hipSuccess;
+  if (lp->precision == HLP_MIXED) hipLaunchKernelGGL(k_kkt_cols<true>, dim3(nb), dim3(kBlock), 0, lp->stream, a);
+  else hipLaunchKernelGGL(k_kkt_cols<false>, dim3(nb), dim3(kBlock), 0, lp->stream, a);
   return hipGetLastError();
 }
 
@@ -1321,7 +1344,8 @@ hipError_t launch_finalize(hlp_lp* lp, int32_t which, int32_t slot) {
   a.dst = lp->results + (int64_t)slot * NQ;
   int nr = 0;
   const bool f32 = (which & 16) != 0;
-  const int64_t nbp = lp->nbT, nbd = lp->nb_dual_region > 0 ? lp->nb_dual_region : lp->nbA;
+  const int64_t nbp = lp->nb_kkt_region > 0 ? lp->nb_kkt_region : lp->nbT;
+  const int64_t nbd = lp->nb_dual_region > 0 ? lp->nb_dual_region : lp->nbA;
   const int64_t nbx = lp->nb_primal_region > 0 ? lp->nb_primal_region : lp->nbT;
   if (which & 1) a.r[nr++] = make_region(region(lp, R_PRIMAL), nbx, {Q_DX2, Q_XA2}, 0u);
   if (which & 2) {
@@ -1403,11 +1427,8 @@ hipError_t launch_primal32(hlp_lp* lp, const StepArgs& s) {
   if (lp->nbT == 0) return hipSuccess;
   Primal32Args a{reinterpret_cast<const int4*>(lp->rbxT), lp->cp, lp->row, lp->tval32, lp->y32, lp->x32, lp->xa32, lp->c32, lp->lv32, lp->uv32,
                  lp->xbar32, lp->xh32, lp->dx32, region(lp, R_PRIMAL), lp->step, s.j};
-  if (s.residual) {
-    lp->nb_primal_region = lp->nbT;
-    return launch_step_kernel(k_primal32<true, false>, lp->nbT, s, lp->stream, a);
-  }
-  if (lp->panels && lp->ntilesT > 0) {
+  const bool split = lp->panels && lp->ntilesT > 0;
+  if (split) {
     a.rb = reinterpret_cast<const int4*>(lp->rbxR);
     a.cp = lp->cpR;
     a.row = lp->rowR;
@@ -1415,9 +1436,15 @@ hipError_t launch_primal32(hlp_lp* lp, const StepArgs& s) {
     a.partT = reinterpret_cast<const float*>(lp->partT);
     a.PT = lp->dense_PT;
     a.n = lp->n;
+  }
+  if (s.residual) {
+    lp->nb_primal_region = split ? lp->nbR : lp->nbT;
+    if (split) return launch_primal_pair(lp, lp->tval32T, lp->y32, a, k_primal32<true, false>, s);
+    return launch_step_kernel(k_primal32<true, false>, lp->nbT, s, lp->stream, a);
+  }
+  if (split)
     return launch_primal_pair(lp, lp->tval32T, lp->y32, a, lp->nt ? k_primal32<false, true> : k_primal32<false, false>,
                               s);
-  }
   if (lp->panels) a.row = lp->rowc;
   if (lp->nt) return launch_step_kernel(k_primal32<false, true>, lp->nbT, s, lp->stream, a);
   return launch_step_kernel(k_primal32<false, false>, lp->nbT, s, lp->stream, a);

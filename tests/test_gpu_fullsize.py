@@ -64,6 +64,8 @@ def _compare_logs(gpu_log, ref_log, r_tol, omega_tol):
         assert abs(g["omega"] - o["omega"]) <= omega_tol * o["omega"], (g["iter"], g["omega"], o["omega"])
         assert abs(g["r"] - o["r"]) <= r_tol * o["r"], (g["iter"], g["r"], o["r"])
         assert abs(g["r0"] - o["r0"]) <= r_tol * o["r0"], (g["iter"], g["r0"], o["r0"])
+        for key in ("rel_kkt", "rel_gap", "rel_primal", "rel_dual"):
+            assert abs(g[key] - o[key]) <= 1e-8 * o[key] + 1e-15, (g["iter"], key, g[key], o[key])
 
 
 @pytest.mark.timeout(300)
