@@ -48,7 +48,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 HEADLINE = "c3a"
-KERNEL_SOURCES = ("paper_2507_14051_amd/csrc/kernels_iter.hip", "paper_2507_14051_amd/csrc/device.h")
+KERNEL_SOURCES = ("paper_2507_14051_amd/csrc/kernels_iter.hip", "paper_2507_14051_amd/csrc/device.h",
+                  "paper_2507_14051_amd/csrc/abi.cpp")  # the kernels and the layout rules
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_half_steps.md")
 C3B_GOLDEN = os.path.join(ROOT, "tests", "golden", "c3b_setup.json")
 

@@ -107,8 +107,8 @@ typedef struct {
                               of xbar stays in that XCD's L2; the per-panel partial row
                               sums are added in panel order.  -1: automatic (on when
                               8n bytes exceed 8 MiB and long rows hold at least half of
-                              the nonzeros; then 8 ceil(n / 2^21) panels, so a panel's
-                              slice of xbar takes at most 2 MiB); 0: off;
+                              the nonzeros; then 8 ceil(n / 2^20) panels, so a panel's
+                              slice of xbar takes at most 1 MiB); 0: off;
                               k > 0: 8 ceil(k / 8) panels, at most 1024.  Changes only the
                               order in which the row sums are added; -1 */
   int32_t panel_row_min;   /* [setup] rows with more nonzeros than this are "long"

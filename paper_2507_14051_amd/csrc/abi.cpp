@@ -67,7 +67,7 @@ int lanes_for(double mean) {
 int32_t panel_count(int32_t n, const hlp_params* p) {
   int64_t P = 0;
   if (p->column_panels > 0) P = 8 * (((int64_t)p->column_panels + 7) / 8);
-  else if (p->column_panels == -1 && n > (1 << 20)) P = 8 * (((int64_t)n + (1 << 21) - 1) >> 21);
+  else if (p->column_panels == -1 && n > (1 << 20)) P = 8 * (((int64_t)n + (1 << 20) - 1) >> 20);
   return (int32_t)std::min<int64_t>(P, 1024);
 }
 

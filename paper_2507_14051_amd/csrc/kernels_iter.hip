@@ -62,12 +62,26 @@ struct PrimalArgs {
   int32_t PT, n;
 };
 
+// sum over r < cnt of a[r*stride + i], added in order of r; the loads go out
+// eight at a time (one load at a time would cost a memory round trip per term).
+template <typename T>
+__device__ __forceinline__ T strided_sum(const T* __restrict__ a, int32_t cnt, int64_t stride, int i) {
+  T h = T(0);
+  for (int r = 0; r < cnt; r += 8) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = r + u < cnt ? a[(int64_t)(r + u) * stride + i] : T(0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (r + u < cnt) h += v[u];
+  }
+  return h;
+}
+
 // The dense rows' part of column j's product: its slice sums in slice order.
 template <typename T>
 __device__ __forceinline__ T slice_sum(const T* __restrict__ partT, int32_t PT, int32_t n, int j) {
-  T h = T(0);
-  for (int r = 0; r < PT; ++r) h += partT[(int64_t)r * n + j];
-  return h;
+  return strided_sum(partT, PT, n, j);
 }
 
 // MODE 0: plain step; 1: also xhat, x - xhat and the check partials;
@@ -360,9 +374,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_combine(const T* __restrict__ 
 
 template <typename T>
 __device__ __forceinline__ T group_sum(const T* __restrict__ part2, int32_t G, int32_t nD, int d) {
-  T h = T(0);
-  for (int g = 0; g < G; ++g) h += part2[(int64_t)g * nD + d];
-  return h;
+  return strided_sum(part2, G, nD, d);
 }
 
 __device__ __forceinline__ bool is_long(const uint32_t* __restrict__ bits, int i) {

@@ -113,7 +113,7 @@ def test_c3b_scaling_stepsize_and_first_100_iterations_match_oracle():
     assert g["workload"] == f"c3b: m={lp.m} n={lp.n} nnz={lp.nnz}"
     announce(f"c3b full size nnz={lp.nnz}: setup vs stored oracle values")
     prob = problem(lp)
-    assert prob.panels()[0] == 24 and prob.dense()[1] > 0
+    assert prob.panels()[0] == 40 and prob.dense()[1] > 0
     dr, dc, eta, passes = prob.scaling()
     prob.close()
     _match_summary(dr.cpu().numpy(), g["d_r"], 1e-12, "c3b d_r")

@@ -205,14 +205,14 @@ def test_panels_mixed_precision():
 
 def test_panels_automatic_on_large_skewed_lp():
     """The large skewed LP (m=2e6, n=5e6, ~30M nonzeros): the automatic rule
-    takes 24 panels; 200 iterations agree with the unsplit path."""
+    takes 40 panels; 200 iterations agree with the unsplit path."""
     lp = lpgen.config("c3b", seed=1)
     announce(f"panels c3b nnz={lp.nnz}")
     a = problem(lp)
     P, nl = a.panels()
     PD, nd = a.dense()
     lens = np.diff(lp.A.indptr)
-    assert P == 24 and nl == int(((lens > 16) & (lens < 2048)).sum())
+    assert P == 40 and nl == int(((lens > 16) & (lens < 2048)).sum())
     assert PD == 2442 and nd == int((lens >= 2048).sum()) > 0
     _, _, eta, _ = a.scaling()
     oa = np_out(a.solve(tol=0.0, max_iter=200))
@@ -269,7 +269,7 @@ def test_panels_and_dense_rows_on_c3a_full_size():
     a = problem(lp)
     P, nl = a.panels()
     PD, nd = a.dense()
-    assert P == 24 and nd == int((lens >= 2048).sum()) and nl == int(((lens > 16) & (lens < 2048)).sum())
+    assert P == 40 and nd == int((lens >= 2048).sum()) and nl == int(((lens > 16) & (lens < 2048)).sum())
     _, _, eta, _ = a.scaling()
     oa = np_out(a.solve(tol=0.0, max_iter=130))
     a.close()
@@ -309,7 +309,7 @@ def test_more_dense_rows_than_reserved_raise_the_threshold():
     announce(f"panels dense overflow (c3b): threshold 20 -> {Ld}")
     a = problem(lp, dense_row_min=20)
     assert a.dense() == (2442, int((lens >= Ld).sum()))
-    assert a.panels() == (24, int(((lens > 16) & (lens < Ld)).sum()))
+    assert a.panels() == (40, int(((lens > 16) & (lens < Ld)).sum()))
     _, _, eta, _ = a.scaling()
     oa = np_out(a.solve(tol=0.0, max_iter=70))
     a.close()
