@@ -289,12 +289,9 @@ struct PanelDotArgs {
   int32_t off[9];
 };
 
-template <typename T, bool NT, typename V = T>
-__global__ __launch_bounds__(kBlock) void k_panel_dot(PanelDotArgs<T, V> p) {
-  __shared__ T lds[kRbLds];
-  const int x = blockIdx.x & 7;
-  const int k = p.off[x] + (int)(blockIdx.x >> 3);
-  if (k >= p.off[x + 1]) return;  // uniform over the block
+// Block k of the (panel, long row) table.
+template <typename T, bool NT, typename V>
+__device__ __forceinline__ void panel_dot_block(const PanelDotArgs<T, V>& p, int k, T* lds) {
   const int4 blk = p.tab[k];
   const int r = blk.x + threadIdx.x;
   const bool own = r < blk.y;
@@ -302,6 +299,16 @@ __global__ __launch_bounds__(kBlock) void k_panel_dot(PanelDotArgs<T, V> p) {
   if (own) { a0 = p.pp[r]; a1 = p.pp[r + 1]; }
   const T acc = rb_dot<T, NT>(p.pcol, p.pval, p.vec, blk.z, blk.w, a0, a1, own, blk.y - blk.x, lds);
   if (own) p.out[r] = acc;
+}
+
+// (Setup's power iteration; the plain half-steps run these blocks in k_dual_ps.)
+template <typename T, bool NT, typename V = T>
+__global__ __launch_bounds__(kBlock) void k_panel_dot(PanelDotArgs<T, V> p) {
+  __shared__ T lds[kRbLds];
+  const int x = blockIdx.x & 7;
+  const int k = p.off[x] + (int)(blockIdx.x >> 3);
+  if (k >= p.off[x + 1]) return;  // uniform over the block
+  panel_dot_block<T, NT>(p, k, lds);
 }
 
 template <typename T>
@@ -391,6 +398,38 @@ struct DualPanelArgs {
   int32_t P, nL, nbS, j, m, nbC, nD, G;
 };
 
+// The dual update of row i (l >= 0: row l of lrow, whose compact copy the
+// primal half-step gathers).
+__device__ __forceinline__ void dual_pn_update(const DualPanelArgs& p, int i, int l, double h, double yi, double lo,
+                                               double hi, double yai) {
+  const double sigma = p.step->sigma, gam = p.step->gamma, a = halpern_a(p.step, p.j);
+  const double w = h - yi / sigma;
+  const double yh = sigma * (clampv(w, lo, hi) - w);
+  const double yn = a * ((1.0 + gam) * yh - gam * yi) + (1.0 - a) * yai;
+  p.y[i] = yn;
+  if (l >= 0) p.y[p.m + l] = yn;
+}
+
+// Row block b of AS: the short rows' products and updates.
+template <bool NT>
+__device__ __forceinline__ void short_block(const DualPanelArgs& p, int b, double* lds) {
+  const int4 blk = p.rb[b];
+  const int i = blk.x + threadIdx.x;
+  const bool in = i < blk.y;
+  bool own = false;
+  double yi = 0.0, lo = 0.0, hi = 0.0, yai = 0.0;
+  int a0 = 0, a1 = 0;
+  if (in) {
+    a0 = p.sp[i]; a1 = p.sp[i + 1];
+    own = !is_long(p.lbits, i);
+    if (own) { yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i]; }
+  }
+  const double h = rb_dot<double, NT>(p.scol, p.sval, p.xbar, blk.z, blk.w, a0, a1, in, blk.y - blk.x, lds);
+  if (own) dual_pn_update(p, i, -1, h, yi, lo, hi, yai);
+}
+
+// Blocks [0, nbS): short rows; then the long rows from their panel partials
+// (h = sum in panel order) and the dense rows from their group sums.
 template <bool NT>
 __global__ __launch_bounds__(kBlock) void k_dual_pn(DualPanelArgs p) {
   __shared__ double lds[kRbLds];
@@ -398,16 +437,8 @@ __global__ __launch_bounds__(kBlock) void k_dual_pn(DualPanelArgs p) {
   bool own = false;
   double h = 0.0, yi = 0.0, lo = 0.0, hi = 0.0, yai = 0.0;
   if ((int)blockIdx.x < p.nbS) {
-    const int4 blk = p.rb[blockIdx.x];
-    i = blk.x + threadIdx.x;
-    const bool in = i < blk.y;
-    int a0 = 0, a1 = 0;
-    if (in) {
-      a0 = p.sp[i]; a1 = p.sp[i + 1];
-      own = !is_long(p.lbits, i);
-      if (own) { yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i]; }
-    }
-    h = rb_dot<double, NT>(p.scol, p.sval, p.xbar, blk.z, blk.w, a0, a1, in, blk.y - blk.x, lds);
+    short_block<NT>(p, blockIdx.x, lds);
+    return;
   } else if ((int)blockIdx.x < p.nbS + p.nbC) {
     l = ((int)blockIdx.x - p.nbS) * kBlock + threadIdx.x;
     own = l < p.nL;
@@ -426,14 +457,7 @@ __global__ __launch_bounds__(kBlock) void k_dual_pn(DualPanelArgs p) {
       h = group_sum(p.part2, p.G, p.nD, d);
     }
   }
-  if (own) {
-    const double sigma = p.step->sigma, gam = p.step->gamma, a = halpern_a(p.step, p.j);
-    const double w = h - yi / sigma;
-    const double yh = sigma * (clampv(w, lo, hi) - w);
-    const double yn = a * ((1.0 + gam) * yh - gam * yi) + (1.0 - a) * yai;
-    p.y[i] = yn;
-    if (l >= 0) p.y[p.m + l] = yn;  // the compact copy gathered by the primal half-step
-  }
+  if (own) dual_pn_update(p, i, l, h, yi, lo, hi, yai);
 }
 
 // Check iterations with panels: the long and dense rows' sums of one product
@@ -676,6 +700,33 @@ struct Dual32PanelArgs {
   int32_t P, nL, nbS, j, m, nbC, nD, G;
 };
 
+__device__ __forceinline__ void dual32_pn_update(const Dual32PanelArgs& p, int i, int l, float h, float yi, float lo,
+                                                 float hi, float yai, float bi) {
+  const float sigma = (float)p.step->sigma, gam = (float)p.step->gamma, a = (float)halpern_a(p.step, p.j);
+  const float w = h - (bi + yi) / sigma;
+  const float yh = yi + sigma * (clampv(w, lo, hi) - h);
+  const float yn = a * ((1.0f + gam) * yh - gam * yi) + (1.0f - a) * yai;
+  p.y[i] = yn;
+  if (l >= 0) p.y[p.m + l] = yn;
+}
+
+template <bool NT>
+__device__ __forceinline__ void short_block(const Dual32PanelArgs& p, int b, float* lds) {
+  const int4 blk = p.rb[b];
+  const int i = blk.x + threadIdx.x;
+  const bool in = i < blk.y;
+  bool own = false;
+  float yi = 0.0f, lo = 0.0f, hi = 0.0f, yai = 0.0f, bi = 0.0f;
+  int a0 = 0, a1 = 0;
+  if (in) {
+    a0 = p.sp[i]; a1 = p.sp[i + 1];
+    own = !is_long(p.lbits, i);
+    if (own) { yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i]; bi = p.b[i]; }
+  }
+  const float h = rb_dot<float, NT>(p.scol, p.sval, p.xbar, blk.z, blk.w, a0, a1, in, blk.y - blk.x, lds);
+  if (own) dual32_pn_update(p, i, -1, h, yi, lo, hi, yai, bi);
+}
+
 template <bool NT>
 __global__ __launch_bounds__(kBlock) void k_dual32_pn(Dual32PanelArgs p) {
   __shared__ float lds[kRbLds];
@@ -683,16 +734,8 @@ __global__ __launch_bounds__(kBlock) void k_dual32_pn(Dual32PanelArgs p) {
   bool own = false;
   float h = 0.0f, yi = 0.0f, lo = 0.0f, hi = 0.0f, yai = 0.0f, bi = 0.0f;
   if ((int)blockIdx.x < p.nbS) {
-    const int4 blk = p.rb[blockIdx.x];
-    i = blk.x + threadIdx.x;
-    const bool in = i < blk.y;
-    int a0 = 0, a1 = 0;
-    if (in) {
-      a0 = p.sp[i]; a1 = p.sp[i + 1];
-      own = !is_long(p.lbits, i);
-      if (own) { yi = p.y[i]; lo = p.lc[i]; hi = p.uc[i]; yai = p.ya[i]; bi = p.b[i]; }
-    }
-    h = rb_dot<float, NT>(p.scol, p.sval, p.xbar, blk.z, blk.w, a0, a1, in, blk.y - blk.x, lds);
+    short_block<NT>(p, blockIdx.x, lds);
+    return;
   } else if ((int)blockIdx.x < p.nbS + p.nbC) {
     l = ((int)blockIdx.x - p.nbS) * kBlock + threadIdx.x;
     own = l < p.nL;
@@ -711,14 +754,36 @@ __global__ __launch_bounds__(kBlock) void k_dual32_pn(Dual32PanelArgs p) {
       h = group_sum(p.part2, p.G, p.nD, d);
     }
   }
-  if (own) {
-    const float sigma = (float)p.step->sigma, gam = (float)p.step->gamma, a = (float)halpern_a(p.step, p.j);
-    const float w = h - (bi + yi) / sigma;
-    const float yh = yi + sigma * (clampv(w, lo, hi) - h);
-    const float yn = a * ((1.0f + gam) * yh - gam * yi) + (1.0f - a) * yai;
-    p.y[i] = yn;
-    if (l >= 0) p.y[p.m + l] = yn;
+  if (own) dual32_pn_update(p, i, l, h, yi, lo, hi, yai, bi);
+}
+
+// The plain dual half-step's latency-bound blocks in one launch: the long
+// rows' panel blocks and the short rows' blocks (with their update), so the
+// short rows run beside the panels instead of after them.  Block b runs on
+// XCD x = b mod 8 (workgroups are dealt to the XCDs in turn); of XCD x's R
+// slots t = b / 8, the np_x panel blocks of its panels take the slots with
+// floor((t+1) np_x / R) > floor(t np_x / R), spread evenly, so each panel
+// keeps its XCD; the u-th other slot of XCD x takes short block u*8 + x.
+// R = max over x of np_x + ceil((nbS - x) / 8) (host), so every block has a slot.
+template <typename T, typename SA>
+struct DualPsArgs {
+  PanelDotArgs<T> pn;
+  SA s;
+  int32_t R;
+};
+
+template <typename T, bool NT, typename SA>
+__global__ __launch_bounds__(kBlock) void k_dual_ps(DualPsArgs<T, SA> a) {
+  __shared__ T lds[kRbLds];
+  const int x = blockIdx.x & 7, t = blockIdx.x >> 3;
+  const int np = a.pn.off[x + 1] - a.pn.off[x];
+  const int c0 = (int)((int64_t)t * np / a.R), c1 = (int)((int64_t)(t + 1) * np / a.R);
+  if (c1 > c0) {  // uniform over the block
+    panel_dot_block<T, NT>(a.pn, a.pn.off[x] + c0, lds);
+    return;
   }
+  const int g = (t - c0) * 8 + x;
+  if (g < a.s.nbS) short_block<NT>(a.s, g, lds);
 }
 
 // Column side of the KKT error at (xhat, yhat): g~ = c~ - A~^T yhat,
@@ -1084,20 +1149,22 @@ hipError_t launch_step_kernel(K kernel, int32_t nblk, const StepArgs& s, hipStre
   return hipGetLastError();
 }
 
-// The launches of a panel half-step: dense tiles and their group sums (if
-// dense rows), the long rows' panel dots (if long rows), then the row
-// updates.  With events, the start event takes the first kernel's start and
-// the stop event the last kernel's end.
+// The launches of a panel half-step: the dense tiles (if dense rows), the
+// panel and short blocks (k_dual_ps), the dense rows' group sums, then the
+// long and dense rows' updates (kdual over its blocks past nbS).  With events,
+// the start event takes the first kernel's start and the stop event the last
+// kernel's end.
 template <typename T, typename KD, typename AD>
 hipError_t launch_panel_dual(hlp_lp* lp, const T* pval, const T* pvalD, const T* vec, KD kdual, const AD& ad,
                              const StepArgs& s) {
+  const bool finish = lp->nbC + lp->nbCD > 0;
   StepArgs first = s, mid = s, last = s;
   first.ev_stop = nullptr;
   mid.ev_start = mid.ev_stop = nullptr;
   last.ev_start = nullptr;
   bool started = false;
-  auto take = [&]() -> const StepArgs& {
-    const StepArgs& a = started ? mid : first;
+  auto take = [&](bool is_last) -> StepArgs {
+    StepArgs a = started ? (is_last ? last : mid) : (is_last ? s : first);
     started = true;
     return a;
   };
@@ -1105,23 +1172,42 @@ hipError_t launch_panel_dual(hlp_lp* lp, const T* pval, const T* pvalD, const T*
   if (lp->nD > 0) {
     DenseDotArgs<T> da{reinterpret_cast<const int4*>(lp->tilesD), reinterpret_cast<const int4*>(lp->rbxD), lp->ppD,
                        lp->pcolD, pvalD, vec, reinterpret_cast<T*>(lp->partD), lp->n};
-    e = lp->nt ? launch_step_kernel(k_dense_dot<T, true, kDenseW>, lp->ntilesD, take(), lp->stream, da)
-               : launch_step_kernel(k_dense_dot<T, false, kDenseW>, lp->ntilesD, take(), lp->stream, da);
+    e = lp->nt ? launch_step_kernel(k_dense_dot<T, true, kDenseW>, lp->ntilesD, take(false), lp->stream, da)
+               : launch_step_kernel(k_dense_dot<T, false, kDenseW>, lp->ntilesD, take(false), lp->stream, da);
     if (e != hipSuccess) return e;
+  }
+  DualPsArgs<T, AD> pa{{reinterpret_cast<const int4*>(lp->tabP), lp->pp, lp->pcol, pval, vec,
+                        reinterpret_cast<T*>(lp->ppart), {}},
+                       ad, 0};
+  int64_t R = 0;
+  for (int x = 0; x < 8; ++x) {
+    pa.pn.off[x] = lp->nL > 0 ? lp->poff[x] : 0;
+    const int64_t np = lp->nL > 0 ? lp->poff[x + 1] - lp->poff[x] : 0;
+    R = std::max<int64_t>(R, np + std::max<int64_t>(0, ((int64_t)ad.nbS - x + 7) / 8));
+  }
+  pa.pn.off[8] = lp->nL > 0 ? lp->poff[8] : 0;
+  pa.R = (int32_t)R;
+  if (R > 0) {
+    e = lp->nt ? launch_step_kernel(k_dual_ps<T, true, AD>, (int32_t)(8 * R), take(!finish && lp->nD == 0), lp->stream, pa)
+               : launch_step_kernel(k_dual_ps<T, false, AD>, (int32_t)(8 * R), take(!finish && lp->nD == 0), lp->stream, pa);
+    if (e != hipSuccess) return e;
+  }
+  if (lp->nD > 0) {
     const int32_t G = (lp->dense_P + kDenseGroup - 1) / kDenseGroup;
-    hipLaunchKernelGGL(k_dense_combine<T>, dim3(lp->nbCD, G), dim3(kBlock), 0, lp->stream,
-                       reinterpret_cast<const T*>(lp->partD), lp->nD, lp->dense_P, reinterpret_cast<T*>(lp->part2D));
+    const StepArgs ev = take(!finish);
+    if (ev.ev_start || ev.ev_stop)
+      hipExtLaunchKernelGGL(k_dense_combine<T>, dim3(lp->nbCD, G), dim3(kBlock), 0, lp->stream, ev.ev_start,
+                            ev.ev_stop, 0, reinterpret_cast<const T*>(lp->partD), lp->nD, lp->dense_P,
+                            reinterpret_cast<T*>(lp->part2D));
+    else
+      hipLaunchKernelGGL(k_dense_combine<T>, dim3(lp->nbCD, G), dim3(kBlock), 0, lp->stream,
+                         reinterpret_cast<const T*>(lp->partD), lp->nD, lp->dense_P, reinterpret_cast<T*>(lp->part2D));
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if (lp->nL > 0) {
-    PanelDotArgs<T> pa{reinterpret_cast<const int4*>(lp->tabP), lp->pp, lp->pcol, pval, vec,
-                       reinterpret_cast<T*>(lp->ppart), {}};
-    for (int k = 0; k < 9; ++k) pa.off[k] = lp->poff[k];
-    e = lp->nt ? launch_step_kernel(k_panel_dot<T, true>, lp->nbPgrid, take(), lp->stream, pa)
-               : launch_step_kernel(k_panel_dot<T, false>, lp->nbPgrid, take(), lp->stream, pa);
-    if (e != hipSuccess) return e;
-  }
-  return launch_step_kernel(kdual, lp->nbS + lp->nbC + lp->nbCD, started ? last : s, lp->stream, ad);
+  if (!finish) return hipSuccess;
+  AD f = ad;
+  f.nbS = 0;
+  return launch_step_kernel(kdual, lp->nbC + lp->nbCD, take(true), lp->stream, f);
 }
 
 // The primal half-step with dense rows: the tiles of ATD (slices of the
