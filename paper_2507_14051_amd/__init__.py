@@ -70,14 +70,16 @@ class Problem:
         # layout: "rows" sizes the column-panel layout for this matrix's rows
         # (hlp_workspace_bytes_csr), "worst" for any rows of its size
         # (hlp_workspace_bytes); "auto" takes the worst-case layout when it
-        # fits in three quarters of the free device memory (on the 692M-nonzero
-        # LP it runs the primal half-step 7% faster, measured), else the
-        # row-sized one.
+        # fits in three quarters of the free device memory, counting what
+        # torch's cache holds unused (on the 692M-nonzero LP it runs the primal
+        # half-step 6-7% faster, measured), else the row-sized one.
         worst = hlp_workspace_bytes(self.m, self.n, self.nnz, self.params)
         if layout not in ("auto", "rows", "worst"):
             raise ValueError("layout must be 'auto', 'rows' or 'worst'")
         if layout == "auto":
             free, _ = torch.cuda.mem_get_info(self.device)
+            # memory torch holds in its cache but does not use is free for us too
+            free += torch.cuda.memory_reserved(self.device) - torch.cuda.memory_allocated(self.device)
             layout = "worst" if worst <= 0.75 * free else "rows"
         if layout == "rows":
             rp_host = rp.cpu().numpy() if hasattr(rp, "cpu") else np.asarray(rp)
