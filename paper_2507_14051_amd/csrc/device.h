@@ -168,6 +168,24 @@ __device__ __forceinline__ ACC strided_products(const I* __restrict__ idx, const
   return strided_batches<STRIDE, kRbUnroll, STAGE, NT, ACC>(idx, val, vec, xoff, first, end, lane, lds);
 }
 
+// lds[q0] + lds[q0 + 1] + ... + lds[q1 - 1], added in that order; the reads
+// go out four at a time (one read at a time would wait out the LDS latency
+// for every term).
+template <typename ACC>
+__device__ __forceinline__ ACC lds_row_sum(const ACC* lds, int q0, int q1) {
+  ACC acc = 0;
+  int q = q0;
+  for (; q + 4 <= q1; q += 4) {
+    const ACC v0 = lds[q], v1 = lds[q + 1], v2 = lds[q + 2], v3 = lds[q + 3];
+    acc += v0;
+    acc += v1;
+    acc += v2;
+    acc += v3;
+  }
+  for (; q < q1; ++q) acc += lds[q];
+  return acc;
+}
+
 // Row sums of val .* vec[idx - xoff] (idx: int32, or uint16 offsets into a
 // staged slice) over the calling block's nrows rows with
 // nonzeros [ps, pe); thread t (own: t < nrows) holds the pointers [a0, a1) of
@@ -201,9 +219,7 @@ __device__ __forceinline__ ACC rb_dot(const I* __restrict__ idx, const V* __rest
   }
   strided_products<kBlock, true, NT, ACC>(idx, val, vec, xoff, ps, pe, tid, lds);
   __syncthreads();
-  ACC acc = 0;
-  if (own)
-    for (int q = a0 - ps; q < a1 - ps; ++q) acc += lds[q];
+  const ACC acc = own ? lds_row_sum(lds, a0 - ps, a1 - ps) : ACC(0);
   __syncthreads();
   return acc;
 }

@@ -258,9 +258,7 @@ __device__ __forceinline__ void row_block_run(const int4* tb, int nbk, const I* 
         if (q < len) lds[q] = (T)cur.v[u] * (T)g[u];
       }
       __syncthreads();
-      T acc = T(0);
-      if (own)
-        for (int q = cur.a0 - blk.z; q < cur.a1 - blk.z; ++q) acc += lds[q];
+      const T acc = own ? lds_row_sum(lds, cur.a0 - blk.z, cur.a1 - blk.z) : T(0);
       __syncthreads();
       if (own) out[r] = acc;
       if (pre) cur = nxt;
