@@ -145,3 +145,33 @@ def test_c3b_scaling_stepsize_and_first_100_iterations_match_oracle():
     assert rel(gx, ref.x) <= 1e-10 and rel(gy, ref.y) <= 1e-10
     print(f"c3b: worst trajectory error over {len(at)} sampled iterations {worst:.1e}; "
           f"checks {[(e['iter'], e['restart']) for e in glog]}")
+
+
+@pytest.mark.timeout(600)
+def test_c3a_scaling_stepsize_and_first_iterations_match_oracle():
+    """The largest LP (m=2e6, n=5e6, 692M nonzeros, int32 offsets near 7e8)
+    in the bench's layout (wide and narrow panels, the split transpose):
+    scaling diagonals, stepsize and the first iterates against the oracle's
+    stored values (sampled entries and norms)."""
+    g = _golden("c3a_setup.json")
+    lp = lpgen.config("c3a", seed=1)
+    assert g["workload"] == f"c3a: m={lp.m} n={lp.n} nnz={lp.nnz}"
+    announce(f"c3a full size nnz={lp.nnz}: setup vs stored oracle values")
+    prob = problem(lp)
+    assert prob.panels()[0] == 40 and prob.dense()[1] > 0
+    dr, dc, eta, passes = prob.scaling()
+    prob.close()
+    _match_summary(dr.cpu().numpy(), g["d_r"], 1e-12, "c3a d_r")
+    _match_summary(dc.cpu().numpy(), g["d_c"], 1e-12, "c3a d_c")
+    print(f"c3a eta {eta!r} vs oracle {g['eta']!r}; power passes {passes} vs {g['power_passes']}")
+    assert eta == pytest.approx(g["eta"], rel=1e-9)
+    assert abs(passes - g["power_passes"]) <= 1
+    T = g["iters"]
+    prob = problem(lp, eta=g["eta"])
+    out = prob.solve(tol=0.0, max_iter=T, trace_iters=T, want_r=False)
+    for t in range(T):
+        for key in ("xh", "yh", "x", "y"):
+            _match_summary(out["trace"][key][t].cpu().numpy(), g["trajectory"][t][key], 1e-10, f"c3a {key} t={t + 1}")
+    print(f"c3a relative KKT after {T} iterations {out['info']['rel_kkt']!r} vs oracle {g['final_rel_kkt']!r}")
+    assert out["info"]["rel_kkt"] == pytest.approx(g["final_rel_kkt"], rel=1e-8)
+    prob.close()
