@@ -169,8 +169,8 @@ __device__ __forceinline__ ACC strided_products(const I* __restrict__ idx, const
 }
 
 // lds[q0] + lds[q0 + 1] + ... + lds[q1 - 1], added in that order; the reads
-// go out four at a time (one read at a time would wait out the LDS latency
-// for every term).
+// go out four at a time, the last one to three together (one read at a time
+// would wait out the LDS latency for every term).
 template <typename ACC>
 __device__ __forceinline__ ACC lds_row_sum(const ACC* lds, int q0, int q1) {
   ACC acc = 0;
@@ -182,7 +182,12 @@ __device__ __forceinline__ ACC lds_row_sum(const ACC* lds, int q0, int q1) {
     acc += v2;
     acc += v3;
   }
-  for (; q < q1; ++q) acc += lds[q];
+  if (q < q1) {  // the last one to three, also read together
+    const ACC v0 = lds[q], v1 = q + 1 < q1 ? lds[q + 1] : ACC(0), v2 = q + 2 < q1 ? lds[q + 2] : ACC(0);
+    acc += v0;
+    if (q + 1 < q1) acc += v1;
+    if (q + 2 < q1) acc += v2;
+  }
   return acc;
 }
 
