@@ -268,10 +268,13 @@ def measure_skewed(dev, lp, name, rate_iters, time_limit, profile_iters):
     return out
 
 
-def measure_c2(dev, steps, profile_iters):
+def measure_c2(dev, steps, profile_iters, with_cpu=True, cpu_iters=50):
     """The medium LP, whose ~38 MB working set stays in the 256 MB Infinity
     Cache: FP64 and FP32 solves to 1e-8 and the FP64 half-steps' rates
-    (cache-resident, not HBM-bound)."""
+    (cache-resident, not HBM-bound); with_cpu: the oracle's time per
+    iteration on the same LP (cpu_iters iterations after its own scaling, a
+    fixed stepsize, one thread) and the time to 1e-8 it implies at the GPU's
+    iteration count (extrapolated, not run)."""
     import torch
     import lpgen
     from paper_2507_14051_amd import MIXED, OPTIMAL, Problem
@@ -303,7 +306,19 @@ def measure_c2(dev, steps, profile_iters):
                             "iters_per_s": round(mi[-1]["iters"] / t32, 1),
                             "time_to_tol_vs_fp64": round(t64 / t32, 3)},
            "half_steps": rf}
-    log(f"# c2: {out['fp64']} {out['fp32_refined']}")
+    if with_cpu:
+        import oracle
+        res = oracle.solve(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv,
+                           oracle.Params(tol=0.0, max_iter=cpu_iters, eta_override=0.5))
+        per_iter = res.info["iter_s"] / cpu_iters
+        out["cpu_oracle"] = {"iter_ms": round(per_iter * 1e3, 3), "cores": 1, "kind": "oracle",
+                             "time_to_tol_s_extrapolated": round(per_iter * infos[-1]["iters"], 1),
+                             "gpu_fp64_speedup_to_tol": round(per_iter * infos[-1]["iters"] / t64, 1),
+                             "sample": f"{cpu_iters} oracle iterations (NumPy/SciPy FP64, one thread) on the whole "
+                                       f"LP after its own scaling ({res.info['setup_s']:.1f} s, not counted), "
+                                       f"fixed stepsize; time to 1e-8 = time per iteration x the "
+                                       f"{infos[-1]['iters']} iterations of the solve (not run)"}
+    log(f"# c2: {out['fp64']} {out['fp32_refined']} {out.get('cpu_oracle')}")
     return out
 
 
@@ -560,7 +575,7 @@ def main():
     extra = {}
     if not args.no_extra:
         extra["c3b"] = measure_skewed(dev, gen("c3b"), "c3b", 640, args.time_limit_c3b, args.profile_iters)
-        extra["c2_cache_resident"] = measure_c2(dev, 2, 400)
+        extra["c2_cache_resident"] = measure_c2(dev, 2, 400, with_cpu=not args.no_cpu)
         if not args.no_adjoint:
             extra["adjoint"] = measure_adjoint(dev)
 
