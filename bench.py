@@ -122,7 +122,11 @@ def reserve_device_memory(dev, lp):
     ws = max(hlp_workspace_bytes(lp.m, lp.n, lp.nnz, hlp_params_default()),
              hlp_workspace_bytes(lp.m, lp.n, lp.nnz, hlp_params_default(precision=MIXED)))
     inputs = 12 * lp.nnz + 4 * (lp.m + 1) + 8 * (3 * lp.n + 2 * lp.m)
-    r = torch.empty(ws + inputs + (1 << 30), dtype=torch.uint8, device=dev)
+    try:
+        r = torch.empty(ws + inputs + (1 << 30), dtype=torch.uint8, device=dev)
+    except torch.cuda.OutOfMemoryError:
+        log(f"# could not reserve {(ws + inputs) / 1e9:.1f} GB up front; each problem allocates its own")
+        return
     del r
     log(f"# reserved {(ws + inputs) / 1e9:.1f} GB of device memory for the run")
 
