@@ -84,10 +84,16 @@ def algorithmic_bytes(m, n, nnz, fp=8):
 
 
 def kernel_source_hash():
+    """Hash of the kernel and layout sources with comments and blank space
+    removed, so that an edit of a comment keeps a traffic record valid and an
+    edit of the code does not."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -272,14 +272,14 @@ __device__ __forceinline__ void row_block_run(const int4* tb, int nbk, const I* 
   }
 }
 
-// Dual half-step with the long rows split into column panels (plain
-// iterations only).  k_panel_dot reduces each (panel, long row) segment; the
-// blocks of panel p run on XCD p mod 8 (workgroups are dealt to the XCDs in
-// turn), so an XCD gathers from one panel's slice of xbar at a time and the
-// slice stays in its L2.  k_dual_pn then does the short rows as k_dual does and,
-// in extra blocks, the long rows: h = sum of the panel partials in panel order.
-// (One row block per workgroup: these gathers go to L2 and want many waves in
-// flight, more than row_block_run's register budget leaves.)
+// Dual half-step with the long rows split into column panels.  A panel block
+// reduces (panel, long row) segments; the blocks of panel p run on XCD p mod 8
+// (workgroups are dealt to the XCDs in turn), so an XCD gathers from one
+// panel's slice of xbar at a time and the slice stays in its L2.  In plain
+// iterations k_dual_ps runs them beside the short rows' blocks; k_dual_pn then
+// adds, for each long row, the panel partials in panel order (h) and runs its
+// update.  (One row block per workgroup: these gathers go to L2 and want many
+// waves in flight, more than row_block_run's register budget leaves.)
 // (T: products and sums; V: the values and the vector.)
 template <typename T, typename V = T>
 struct PanelDotArgs {
@@ -299,7 +299,8 @@ __device__ __forceinline__ void panel_dot_block(const PanelDotArgs<T, V>& p, int
   if (own) p.out[r] = acc;
 }
 
-// (Setup's power iteration; the plain half-steps run these blocks in k_dual_ps.)
+// (The power iteration's and the check iterations' products; the plain
+// half-step runs these blocks in k_dual_ps.)
 template <typename T, bool NT, typename V = T>
 __global__ __launch_bounds__(kBlock) void k_panel_dot(PanelDotArgs<T, V> p) {
   __shared__ T lds[kRbLds];
