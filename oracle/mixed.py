@@ -133,6 +133,8 @@ def solve_mixed(A, c, lc, uc, lv, uv, params: Params | None = None, trace_iters=
         if trace_iters and t <= trace_iters:
             trace["xh"].append(xb + xh.astype(np.float64) / P)
             trace["yh"].append(yb + yh.astype(np.float64) / D)
+        if t in p.trace_at:  # further iterations kept by number (Params.trace_at)
+            trace.setdefault("at", {})[t] = (xb + xh.astype(np.float64) / P, yb + yh.astype(np.float64) / D)
         if not check:
             continue
         xc = xb + xh.astype(np.float64) / P

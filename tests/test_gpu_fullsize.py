@@ -175,3 +175,47 @@ def test_c3a_scaling_stepsize_and_first_iterations_match_oracle():
     print(f"c3a relative KKT after {T} iterations {out['info']['rel_kkt']!r} vs oracle {g['final_rel_kkt']!r}")
     assert out["info"]["rel_kkt"] == pytest.approx(g["final_rel_kkt"], rel=1e-8)
     prob.close()
+
+
+@pytest.mark.timeout(900)
+def test_mixed_c3b_first_100_iterations_match_fp32_oracle():
+    """The FP32 path on the large skewed LP at full size (wide and narrow
+    panels, the split transpose, FP32 partial sums) against the oracle's FP32
+    iteration (oracle/mixed.py) with the oracle's stepsize, over the first
+    100 iterations, with the artificial restart and its re-centring at 64.
+    Both sides sum FP32 products in FP32 but in different orders (panel and
+    slice order here, row order in the oracle), so each row sum differs by
+    rounding of about u * sqrt(L) relative for a row of L terms (u = 6e-8):
+    up to about 1.3e-5 for the 50,000-nonzero rows, about 2e-7 for the short
+    rows that make up most of the vector; over 100 nonexpansive steps the
+    bar is 1e-4 relative in the 2-norm per compared iteration (the medium
+    LP's bar 1e-5 scaled by the longest rows)."""
+    from oracle.mixed import solve_mixed
+    from paper_2507_14051_amd import MIXED
+    g = _golden("c3b_setup.json")
+    lp = lpgen.config("c3b", seed=1)
+    T = 100
+    at = (1, 2, 3, 32, 63, 64, 65, 99, 100)
+    announce(f"mixed c3b full size nnz={lp.nnz}: 100 iterations, GPU and oracle/mixed.py")
+    prob = problem(lp, eta=g["eta"], precision=MIXED)
+    assert prob.panels()[0] == 40 and prob.dense()[1] > 0
+    out = prob.solve(tol=0.0, max_iter=T, trace_iters=T, want_r=False)
+    gtr = {t: [out["trace"][k][t - 1].cpu().numpy() for k in ("xh", "yh")] for t in at}
+    glog = out["log"]
+    prob.close()
+    del out
+    ref = solve_mixed(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv,
+                      Params(tol=0.0, max_iter=T, eta_override=g["eta"], trace_at=at))
+    worst = 0.0
+    for t in at:
+        for key, a, b in zip(("xh", "yh"), gtr[t], ref["trace"]["at"][t]):
+            e = rel(a, b)
+            worst = max(worst, e)
+            assert e <= 1e-4, (t, key, e)
+    assert [e["iter"] for e in glog] == [e["t"] for e in ref["log"]]
+    assert [e["iter"] for e in glog if e["restart"]] == [64]
+    for gl, rl in zip(glog, ref["log"]):
+        assert abs(gl["rel_kkt"] - rl["rel_kkt"]) <= 1e-3 * rl["rel_kkt"], (gl["iter"], gl["rel_kkt"], rl["rel_kkt"])
+    print(f"mixed c3b: worst relative error over {len(at)} sampled iterations vs oracle/mixed.py {worst:.2e}; "
+          f"rel_kkt at the checks {[(e['iter'], e['rel_kkt']) for e in glog]} vs "
+          f"{[(e['t'], e['rel_kkt']) for e in ref['log']]}")
