@@ -222,6 +222,68 @@ def pin_kkt_golden(orc):
         np.testing.assert_array_equal(k["r"], case["r"])
 
 
+# ------------------------------------------------------------------ anchor, PID, power iteration
+def pin_new_anchor_is_pdhg_output(orc):
+    """A restart makes zhat = PDHG(z) the new anchor and the new iterate
+    (Sec. 3, the anchor of the next epoch): with a restart forced at T = 1
+    (beta_artificial = 1, a check every iteration, the primal weight left
+    alone), the second iterate is z^2 = 1/2((1+g) T zhat^1 - g zhat^1) + 1/2 zhat^1."""
+    lp = _tiny(seed=5)
+    A = lp.A.tocsr()
+    AT = lp.A.T.tocsr()
+    omega = 1.3
+    eta, p = _unscaled(orc, lp, tol=1e-300, max_iter=2, eval_freq=1, trace_iters=2, omega0=omega,
+                       beta_sufficient=-1.0, beta_necessary=-1.0, beta_artificial=1.0, kp=0.0, ki=0.0, kd=0.0)
+    res = orc.solve(lp.A, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, p)
+    assert [e["t"] for e in res.log if e["restart"]] == [1]
+    zh1 = np.concatenate([res.trace["xh"][0], res.trace["yh"][0]])
+    xh, yh, _ = orc.pdhg.pdhg_operator(A, AT, lp.c, lp.lv, lp.uv, lp.lc, lp.uc, eta / omega, eta * omega,
+                                       zh1[:lp.n], zh1[lp.n:])
+    g = p.gamma
+    want = 0.5 * ((1 + g) * np.concatenate([xh, yh]) - g * zh1) + 0.5 * zh1
+    got = np.concatenate([res.trace["x"][1], res.trace["y"][1]])
+    np.testing.assert_allclose(got, want, rtol=1e-13, atol=1e-14)
+
+
+def pin_pid_ratio_rule(orc):
+    """Gains (1, 0, 0) give omega = ||dy|| / ||dx|| exactly: with
+    e = log(omega ||dx|| / ||dy||) the update moves log omega by -e."""
+    p = orc.Params(kp=1.0, ki=0.0, kd=0.0)
+    rng = np.random.default_rng(11)
+    for _ in range(10):
+        om, dx, dy = math.exp(rng.uniform(-3, 3)), rng.uniform(0.1, 10), rng.uniform(0.1, 10)
+        got = orc.pdhg.pid_update(om, dx, dy, {}, p)
+        assert abs(got - dy / dx) <= 1e-12 * (dy / dx), (om, dx, dy, got)
+
+
+def pin_pid_sequence(orc):
+    """Two hand-computed PID steps with all three gains (0.5, 0.25, 0.125)
+    from omega = 2: the integral sums the errors including the current one,
+    the derivative term starts at 0."""
+    p = orc.Params(kp=0.5, ki=0.25, kd=0.125)
+    e1 = math.log(2.0 * 1.0 / 3.0)                       # omega 2, dx 1, dy 3
+    om1 = math.exp(math.log(2.0) - (0.5 * e1 + 0.25 * e1))
+    e2 = math.log(om1 * 2.0 / 1.0)                       # dx 2, dy 1
+    om2 = math.exp(math.log(om1) - (0.5 * e2 + 0.25 * (e1 + e2) + 0.125 * (e2 - e1)))
+    st = {}
+    om = 2.0
+    for (dx, dy), want in (((1.0, 3.0), om1), ((2.0, 1.0), om2)):
+        om = orc.pdhg.pid_update(om, dx, dy, st, p)
+        assert abs(om - want) <= 1e-13 * want, (om, want)
+
+
+def pin_power_norm_dense(orc):
+    """The power iteration's estimate of ||A||_2 against the largest singular
+    value of a dense SVD (Sec. 3, stepsize)."""
+    rng = np.random.default_rng(13)
+    M = rng.standard_normal((30, 45)) * (rng.random((30, 45)) < 0.3)
+    est, _ = orc.pdhg.power_norm(sp.csr_matrix(M), 5000, 1e-12)
+    true = float(np.linalg.svd(M, compute_uv=False)[0])
+    assert abs(est - true) <= 1e-6 * true, (est, true)
+
+
 ALL_PINS = [pin_residual_is_p_norm, pin_logged_residual_is_definition, pin_reflected_halpern_closed_form,
             pin_artificial_restart_schedule, pin_counts_after_increment, pin_epoch_bookkeeping,
-            pin_scaling_golden, pin_kkt_golden]
+            pin_scaling_golden, pin_kkt_golden, pin_new_anchor_is_pdhg_output, pin_pid_ratio_rule,
+            pin_pid_sequence, pin_power_norm_dense]
+

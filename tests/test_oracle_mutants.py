@@ -7,7 +7,10 @@ The mistakes are those a reader checking the oracle against the paper by eye
 could miss: a sign, a factor or a swapped pair in r(z) (Sec. 2.2), the
 Halpern weight one step off (Sec. 3), the restart bookkeeping (Sec. 3,
 "Adaptive restart"), the Pock-Chambolle pass without its root or with maxima,
-and the duality-gap denominator (Sec. 4).
+and the duality-gap denominator (Sec. 4); the PID update's sign, error and
+integral, the new anchor at a restart and the sign of the reflection (Sec.
+3); the power iteration's square root (Sec. 3, stepsize); the primal bound
+norm and the projected dual residual of the KKT error (Sec. 4).
 """
 import importlib
 import itertools
@@ -42,7 +45,21 @@ MUTANTS = [
      "rsum = np.asarray(absA.max(axis=1).todense()).ravel()\n"
      "        csum = np.asarray(absA.max(axis=0).todense()).ravel()"),
     ("gap_denominator", "kkt.py", "(1.0 + abs(pobj) + abs(dobj))", "(1.0 + abs(pobj - dobj))"),
+    ("pid_sign", "pdhg.py", "math.exp(math.log(omega) - (p.kp * e", "math.exp(math.log(omega) + (p.kp * e"),
+    ("pid_error_inverted", "pdhg.py", "e = math.log(omega * dxn / dyn)", "e = math.log(omega * dyn / dxn)"),
+    ("pid_integral_lags", "pdhg.py", 'state["sum"] = state.get("sum", 0.0) + e',
+     'state["sum"] = state.get("sum", 0.0) + (state.get("prev") or 0.0)'),
+    ("anchor_is_halpern_iterate", "pdhg.py", "            if p.restart_to_current:\n",
+     "            if not p.restart_to_current:\n"),
+    ("reflection_sign", "pdhg.py", "x = a * ((1.0 + gam) * xh - gam * x) + (1.0 - a) * xa",
+     "x = a * ((1.0 - gam) * xh + gam * x) + (1.0 - a) * xa"),
+    ("power_norm_squared", "pdhg.py", "    return math.sqrt(s), it", "    return s, it"),
+    ("primal_bound_norm_lower_only", "kkt.py",
+     "bnd = np.concatenate([lc[np.isfinite(lc)], uc[np.isfinite(uc)]])", "bnd = lc[np.isfinite(lc)]"),
+    ("dual_residual_unprojected", "kkt.py", "rho_d = float(np.linalg.norm(g - r))",
+     "rho_d = float(np.linalg.norm(g))"),
 ]
+
 
 _counter = itertools.count()
 
