@@ -88,6 +88,17 @@ def test_panels_skewed_rows_match_oracle(K):
     _end_point_case(lp, K, panels=16, row_min=8)
 
 
+@pytest.mark.parametrize("panels", [1, 1024])
+def test_panels_count_extremes(panels):
+    """The fewest (8) and the most (1024) wide panels: with 1024 panels of 20
+    columns most (panel, long row) segments are empty and each XCD holds 128
+    panels, so the slots of k_dual_ps are mostly panel blocks; with 8 panels
+    one per XCD."""
+    lp = lpgen.gen(3000, 20000, zipf_alpha=1.3, cap=9000, eq_frac=0.3, free_frac=0.2, values="normal", seed=9)
+    announce(f"panels count {panels} nnz={lp.nnz}")
+    _end_point_case(lp, 130, panels=panels, row_min=8, dense_min=1024)
+
+
 @pytest.mark.parametrize("dense_min", [0, 512])
 def test_panels_long_and_dense_rows(dense_min):
     """Rows above 512 nonzeros in the narrow LDS-staged panels, the rest of the
